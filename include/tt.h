@@ -1,0 +1,183 @@
+/* tt.h - C ABI of the MI355X (gfx950) solver for linear systems with
+ * Kronecker product structure (Chen & Kressner, "Recursive blocked algorithms
+ * for linear systems with Kronecker product structure", arXiv 1905.09539).
+ *
+ * Equations (paper notation; X x_mu A is the mu-mode product of Sec. 2,
+ * defined by (X x_mu A)_(mu) = A X_(mu)):
+ *
+ *   Laplace-like form, eq. (1.4) / (2.2):
+ *       X x_1 A_1 + X x_2 A_2 + ... + X x_d A_d = B
+ *   Pair form (the family with two matrices per mode, Conclusions):
+ *       sum_mu X x_1 C_1 ... x_mu A_mu ... x_d C_d = B
+ *
+ * Conventions shared by every entry point
+ *   - d is the tensor order, 1 <= d <= 4; n[0..d-1] are the mode sizes
+ *     (n[mu] >= 0; a zero-sized mode makes the call a no-op).
+ *   - Tensors (B, X, G, dB, ...) are DEVICE pointers to float64 data in
+ *     C order: the LAST mode is the fastest, element (i_1..i_d) sits at
+ *     sum_mu i_mu * prod_{nu > mu} n[nu].  This is the reverse of the
+ *     paper's column-major vec(); the solution is the same tensor.
+ *   - Coefficients are passed as a HOST array of d DEVICE pointers, each to a
+ *     row-major n[mu] x n[mu] float64 matrix.
+ *   - "Upper quasi-triangular" is the real Schur form of Sec. 2 (Algorithm 1):
+ *     zero below the first subdiagonal, and no two consecutive nonzero
+ *     subdiagonal entries; a nonzero T[i+1][i] marks a 2x2 diagonal block.
+ *   - The caller owns every buffer; the library keeps no pointer to caller
+ *     memory after a call returns (plans keep only their own copies).
+ *   - Work is ordered on opts->stream (NULL = the null stream).  The
+ *     solve_* calls synchronise that stream once at the end to read the
+ *     device status word; tt_plan_solve does not (see tt_plan_status).
+ *   - Every function returns a tt_status; no exception crosses the ABI.
+ *     tt_last_error() returns a thread-local description of the last failure.
+ *   - Not re-entrant on one plan: calls that share a plan must be ordered.
+ */
+#ifndef TT_H_
+#define TT_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TT_OK = 0,
+    TT_EINVAL = 1,      /* bad argument, shape or coefficient structure      */
+    TT_ESINGULAR = 2,   /* an eigenvalue sum vanished (uniqueness fails,
+                           Sec. 2) or a non-finite value appeared            */
+    TT_ENOMEM = 3,      /* device or host allocation failed                 */
+    TT_EHIP = 4,        /* a HIP runtime call failed                        */
+    TT_ENOTCONV = 5     /* mixed-precision refinement did not reach tol     */
+} tt_status;
+
+typedef enum {
+    TT_FP64 = 0,        /* all arithmetic in float64                         */
+    TT_MP_FP32 = 1,     /* updates/transforms in FP32, FP64 refinement       */
+    TT_MP_BF16 = 2      /* updates/transforms in BF16 MFMA, FP64 refinement  */
+} tt_prec;
+
+typedef struct {
+    int nmin;           /* leaf block edge per mode (the paper's n_min,
+                           Algorithm 2); 0 = default (16 for d<=3, 8 for d=4) */
+    int prec;           /* tt_prec                                           */
+    double tol;         /* refinement stop: ||D||_F / ||X||_F <= tol         */
+    int max_iter;       /* refinement iteration cap                          */
+    void* stream;       /* hipStream_t                                       */
+    double info[4];     /* out: [0] refinement iterations, [1] last
+                           ||D||_F/||X||_F, [2] plan build seconds,
+                           [3] device solve milliseconds (when timed)        */
+} tt_opts;
+
+/* Fill *o with defaults (nmin 0, TT_FP64, tol 1e-13, max_iter 10, stream NULL). */
+int tt_opts_default(tt_opts* o);
+
+/* Human-readable name of a status code (static storage). */
+const char* tt_status_str(int status);
+
+/* Thread-local message describing the last failure on this thread. */
+const char* tt_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * solve_tri_tensor - triangular solve (Algorithm 2 of the paper, recursion on
+ * the largest mode with the bump-aware split of Sec. 2.1, with Algorithm 3's
+ * merging of small modes).
+ *   T[mu]: upper quasi-triangular coefficients A_mu (device).
+ *   C:     NULL for the Laplace-like form, else a host array of d device
+ *          pointers to UPPER TRIANGULAR C_mu (pair form).
+ *   B:     right-hand side (device, read only unless X == B).
+ *   X:     solution (device); X may alias B.
+ * Errors: TT_EINVAL (d, n, NULL pointer, T not quasi-triangular, C not
+ * triangular), TT_ESINGULAR (zero pivot or non-finite result; X content is
+ * then unspecified), TT_ENOMEM, TT_EHIP.
+ * ------------------------------------------------------------------------- */
+int solve_tri_tensor(int d, const int64_t* n, const double* const* T,
+                     const double* const* C, const double* B, double* X,
+                     tt_opts* opts);
+
+/* ---------------------------------------------------------------------------
+ * solve_general_tensor - Algorithm 1 of the paper for dense coefficients:
+ * real Schur decomposition A_mu = U_mu T_mu U_mu^T on the host (Hessenberg
+ * reduction + Francis double-shift QR), B~ = B x_1 U_1^T ... x_d U_d^T on the
+ * GPU, the triangular solve, and X = X~ x_1 U_1 ... x_d U_d on the GPU.
+ *   A_host[mu]: HOST pointers to dense row-major n[mu] x n[mu] matrices.
+ *   B, X: device tensors; X may alias B.
+ * opts->prec selects FP64 or mixed precision with FP64 iterative refinement
+ * (residual B - sum_mu X x_mu A_mu always in FP64); opts->info[0..1] report
+ * the iterations and the last correction ratio.
+ * Errors: as solve_tri_tensor, plus TT_EINVAL if the QR iteration does not
+ * converge, TT_ENOTCONV if refinement stops above opts->tol.
+ * ------------------------------------------------------------------------- */
+int solve_general_tensor(int d, const int64_t* n, const double* const* A_host,
+                         const double* B, double* X, tt_opts* opts);
+
+/* ---------------------------------------------------------------------------
+ * solve_backward - adjoint of solve_tri_tensor (Laplace-like form) for a
+ * scalar loss L with dL/dX = G:
+ *   Lam solves sum_mu Lam x_mu T_mu^T = G   (lower quasi-triangular system),
+ *   dB = Lam,
+ *   dT[mu] = -Lam_(mu) X_(mu)^T, masked to the quasi-triangular pattern of
+ *            T[mu] (upper triangle + nonzero bump subdiagonal) unless
+ *            dense_grad != 0.
+ *   X: the forward solution (device).  dB: device tensor (may alias G).
+ *   dT: host array of d device pointers to n[mu] x n[mu] outputs, or NULL to
+ *       skip the coefficient gradients; individual entries may be NULL.
+ * Errors: as solve_tri_tensor.
+ * ------------------------------------------------------------------------- */
+int solve_backward(int d, const int64_t* n, const double* const* T,
+                   const double* X, const double* G, double* dB,
+                   double* const* dT, int dense_grad, tt_opts* opts);
+
+/* Batched forms: count independent problems of possibly different shapes,
+ * solved together (one launch sequence for the whole batch).  d[b], n[b],
+ * T[b], B[b], X[b] describe problem b exactly as in solve_tri_tensor
+ * (Laplace-like form only).  dT may be NULL; dT[b] follows solve_backward. */
+int solve_tri_tensor_batched(int count, const int* d, const int64_t* const* n,
+                             const double* const* const* T,
+                             const double* const* B, double* const* X,
+                             tt_opts* opts);
+int solve_backward_batched(int count, const int* d, const int64_t* const* n,
+                           const double* const* const* T,
+                           const double* const* X, const double* const* G,
+                           double* const* dB, double* const* const* dT,
+                           int dense_grad, tt_opts* opts);
+
+/* ---------------------------------------------------------------------------
+ * Plans: the split/merge schedule and the coefficient structure of
+ * solve_tri_tensor, built once and executed many times (host work and the
+ * only device->host copies happen in tt_plan_create).
+ *   tt_plan_create reads T (and C) from the device, validates them and keeps
+ *     device copies; trans != 0 plans the adjoint system with T_mu^T.
+ *   tt_plan_solve  enqueues the solve of B into X on stream (no host sync,
+ *     no allocation); X may alias B.
+ *   tt_plan_status synchronises the stream of the last solve and returns
+ *     TT_ESINGULAR if that solve met a zero pivot or a non-finite value.
+ *   tt_plan_flops  returns the method's flop count (one FMA = 2 flops):
+ *     2 * sum_mu (n_mu (n_mu - 1) / 2 + bumps_mu) * N / n_mu for the
+ *     Laplace-like form.
+ * ------------------------------------------------------------------------- */
+typedef struct tt_plan_s* tt_plan;
+
+int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T,
+                   const double* const* C, int trans, const tt_opts* opts);
+int tt_plan_create_batched(tt_plan* out, int count, const int* d,
+                           const int64_t* const* n, const double* const* const* T,
+                           int trans, const tt_opts* opts);
+int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream);
+int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X,
+                          void* stream);
+int tt_plan_status(tt_plan plan);
+/* Profiling pass: the same work as tt_plan_solve with HIP timing events
+ * around every kernel launch; synchronises.  out[12] receives, for kernel
+ * class k (0 = leaf solves, 1 = recursion updates): out[4k] summed launch
+ * milliseconds, out[4k+1] algorithmic flops, out[4k+2] algorithmic HBM bytes,
+ * out[4k+3] launches; out[8] = milliseconds from the first leaf launch to the
+ * end of the last one. */
+int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, double* out);
+double tt_plan_flops(tt_plan plan);
+int tt_plan_destroy(tt_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TT_H_ */

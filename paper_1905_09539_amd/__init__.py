@@ -1,0 +1,214 @@
+"""Python binding of libtt.so, the MI355X (gfx950) solver for linear systems
+with Kronecker product structure (Chen & Kressner, arXiv 1905.09539).
+
+This module only marshals arguments: every step of the solve runs in the HIP
+kernels of libtt.so (see include/tt.h).  PyTorch provides device memory and
+streams.  There is no CPU fallback: if libtt.so is missing, importing the
+solver functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libtt.so")
+
+TT_OK, TT_EINVAL, TT_ESINGULAR, TT_ENOMEM, TT_EHIP, TT_ENOTCONV = range(6)
+TT_FP64, TT_MP_FP32, TT_MP_BF16 = 0, 1, 2
+
+
+class TTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_STATUS = {0: "TT_OK", 1: "TT_EINVAL", 2: "TT_ESINGULAR", 3: "TT_ENOMEM", 4: "TT_EHIP", 5: "TT_ENOTCONV"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("nmin", ctypes.c_int), ("prec", ctypes.c_int), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("info", ctypes.c_double * 4)]
+
+
+_lib = None
+
+# exported C symbols declared in include/tt.h
+SYMBOLS = [
+    "tt_opts_default", "tt_status_str", "tt_last_error", "solve_tri_tensor",
+    "solve_general_tensor", "solve_backward", "solve_tri_tensor_batched",
+    "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
+    "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
+    "tt_schedule_info", "tt_plan_profile",
+]
+
+
+def lib():
+    """Load libtt.so (built by build.py / __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise ImportError(f"{_SO} is missing: build it with python -m paper_1905_09539_amd.build")
+        L = ctypes.CDLL(_SO)
+        vp, i64p, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)
+        L.tt_last_error.restype = ctypes.c_char_p
+        L.tt_status_str.restype = ctypes.c_char_p
+        L.tt_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.solve_tri_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_general_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_backward.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts)]
+        L.solve_tri_tensor_batched.argtypes = [ctypes.c_int, ip, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_backward_batched.argtypes = [ctypes.c_int, ip, vp, vp, vp, vp, vp, vp, ctypes.c_int,
+                                             ctypes.POINTER(Opts)]
+        L.tt_plan_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp, ctypes.c_int,
+                                     ctypes.POINTER(Opts)]
+        L.tt_plan_create_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ip, vp, vp, ctypes.c_int,
+                                             ctypes.POINTER(Opts)]
+        L.tt_plan_solve.argtypes = [vp, vp, vp, vp]
+        L.tt_plan_solve_batched.argtypes = [vp, vp, vp, vp]
+        L.tt_plan_status.argtypes = [vp]
+        L.tt_plan_flops.argtypes = [vp]
+        L.tt_plan_flops.restype = ctypes.c_double
+        L.tt_plan_destroy.argtypes = [vp]
+        L.tt_plan_profile.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.tt_schedule_info.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != TT_OK:
+        raise TTError(rc, lib().tt_last_error().decode())
+
+
+def _shape(shape):
+    return (ctypes.c_int64 * len(shape))(*[int(x) for x in shape])
+
+
+def _ptr_array(ptrs):
+    return (ctypes.c_void_p * len(ptrs))(*ptrs)
+
+
+def _dev(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _opts(nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None):
+    o = Opts()
+    lib().tt_opts_default(ctypes.byref(o))
+    o.nmin, o.prec, o.tol, o.max_iter = int(nmin), int(prec), float(tol), int(max_iter)
+    o.stream = _stream(stream).value
+    return o
+
+
+def solve_tri(T, B, C=None, X=None, nmin=0, stream=None):
+    """Solve sum_mu X x_mu T_mu = B (Laplace-like form, eq. (2.2)) or, with
+    C given, the pair form sum_mu X x_1 C_1 .. x_mu T_mu .. x_d C_d = B.
+    T, C: lists of n_mu x n_mu float64 CUDA tensors (T upper quasi-triangular,
+    C upper triangular); B: float64 CUDA tensor of shape (n_1, ..., n_d)."""
+    import torch
+    if X is None:
+        X = torch.empty_like(B)
+    tp = _ptr_array([_dev(t) for t in T])
+    cp = _ptr_array([_dev(c) for c in C]) if C is not None else None
+    o = _opts(nmin=nmin, stream=stream)
+    _check(lib().solve_tri_tensor(B.dim(), _shape(B.shape), tp, cp, _dev(B), _dev(X), ctypes.byref(o)))
+    return X
+
+
+class Plan:
+    """A reusable schedule for solving with fixed coefficients (tt_plan_*)."""
+
+    def __init__(self, T, shape=None, nmin=0, trans=False, batch_T=None, batch_shapes=None):
+        self._h = ctypes.c_void_p()
+        o = _opts(nmin=nmin)
+        if batch_T is None:
+            self._keep = [_ptr_array([_dev(t) for t in T])]
+            self.count = 1
+            self.shapes = [tuple(int(x) for x in shape)]
+            _check(lib().tt_plan_create(ctypes.byref(self._h), len(shape), _shape(shape), self._keep[0], None,
+                                        int(bool(trans)), ctypes.byref(o)))
+        else:
+            self.count = len(batch_T)
+            self.shapes = [tuple(int(x) for x in s) for s in batch_shapes]
+            ds = (ctypes.c_int * self.count)(*[len(s) for s in self.shapes])
+            shp = [_shape(s) for s in self.shapes]
+            shp_arr = (ctypes.c_void_p * self.count)(*[ctypes.cast(s, ctypes.c_void_p).value for s in shp])
+            tarrs = [_ptr_array([_dev(t) for t in Tb]) for Tb in batch_T]
+            t_arr = (ctypes.c_void_p * self.count)(*[ctypes.cast(a, ctypes.c_void_p).value for a in tarrs])
+            self._keep = [shp, tarrs]
+            _check(lib().tt_plan_create_batched(ctypes.byref(self._h), self.count, ds, shp_arr, t_arr,
+                                                int(bool(trans)), ctypes.byref(o)))
+
+    @property
+    def flops(self):
+        return lib().tt_plan_flops(self._h)
+
+    def solve(self, B, X=None, stream=None):
+        """Enqueue the solve (no host synchronisation)."""
+        import torch
+        if self.count == 1:
+            if X is None:
+                X = torch.empty_like(B)
+            _check(lib().tt_plan_solve(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
+                                       _stream(stream)))
+            return X
+        if X is None:
+            X = [torch.empty_like(b) for b in B]
+        bp = _ptr_array([_dev(b) for b in B])
+        xp = _ptr_array([_dev(x) for x in X])
+        _check(lib().tt_plan_solve_batched(self._h, bp, xp, _stream(stream)))
+        return X
+
+    def profile(self, B, X, stream=None):
+        """Run one solve with timing events around every launch; returns per
+        kernel class ("leaf", "update") the summed launch milliseconds,
+        algorithmic flops, algorithmic HBM bytes and launch count."""
+        out = (ctypes.c_double * 12)()
+        _check(lib().tt_plan_profile(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
+                                     _stream(stream), out))
+        res = {}
+        for k, name in enumerate(["leaf", "update"]):
+            res[name] = {"ms": out[4 * k], "flops": out[4 * k + 1], "bytes": out[4 * k + 2],
+                         "launches": int(out[4 * k + 3])}
+        res["leaf_span_ms"] = out[8]
+        return res
+
+    def status(self):
+        _check(lib().tt_plan_status(self._h))
+
+    def close(self):
+        if self._h:
+            lib().tt_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def schedule_info(T_host, shape, nmin=0):
+    """Host-only: statistics and dependency check of the solve schedule for
+    coefficients given as numpy arrays (no GPU needed)."""
+    Th = [np.ascontiguousarray(t, dtype=np.float64) for t in T_host]
+    out = (ctypes.c_double * 13)()
+    _check(lib().tt_schedule_info(len(shape), _shape(shape), _ptr_array([t.ctypes.data for t in Th]),
+                                  int(nmin), out))
+    keys = ["flops", "flops_leaf", "flops_update", "waves", "leaves", "tasks", "items", "launches",
+            "bmax0", "bmax1", "bmax2", "bmax3", "dependency_violation"]
+    return dict(zip(keys, list(out)))

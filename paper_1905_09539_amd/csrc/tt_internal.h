@@ -1,0 +1,127 @@
+// Internal declarations shared by the host planner/API (tt_api.cpp) and the
+// gfx950 kernels (tt_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tt.h"
+
+namespace tt {
+
+constexpr int kMaxD = 4;          // internal order (d < 3 is promoted to 3)
+constexpr int kLeafThreads = 512; // one workgroup per leaf block
+constexpr int kUpdThreads = 256;  // one workgroup per 64x64 update tile
+constexpr int kTile = 64;
+
+// Per-problem description as the kernels see it (device table).
+struct ProbDesc {
+    double* X;                   // solution / right-hand side, in place
+    double* A[kMaxD];            // per-mode update accumulators (modes >= 1;
+                                 // mode 0 updates go straight into X)
+    const double* T[kMaxD];      // coefficients (device, row-major n x n)
+    const int32_t* bst[kMaxD];   // block starts per mode (device), m+1 entries
+    int64_t n[kMaxD];
+    int64_t stride[kMaxD];
+};
+
+// One leaf block: problem index and block coordinates.
+struct LeafDesc {
+    int32_t prob;
+    int16_t blk[kMaxD];
+    int32_t flags;               // bit mu: subtract accumulator A[mu];
+                                 // bit 4+mu: the next block along mu exists
+                                 // (its contribution is applied in the leaf)
+};
+
+// One right-looking update of the dyadic recursion along mode mu:
+//   X[.., r0:r0+M, ..] -= T_mu[r0:r0+M, k0:k0+K] x_mu X[.., k0:k0+K, ..]
+// restricted to one pencil: the product of the blocks of the other modes.
+// ext/ostr list the other modes in increasing mode order (last = fastest).
+struct UpdDesc {
+    int64_t xbase;               // offset of the pencil origin (mode-mu index 0)
+    int32_t prob;
+    int32_t r0, M, k0, K;
+    int32_t P;                   // number of pencil columns = prod(ext)
+    int32_t ext[3];
+    int16_t mode;                // mode mu of the update
+    int16_t flags;               // bit 0: first contribution to these targets
+                                 // (store instead of accumulate)
+    int64_t ostr[3];             // strides of the other modes
+};
+
+// One 64x64 output tile of an update task.
+struct WorkItem {
+    int32_t task;
+    int16_t ta, tb;              // tile indices (meaning depends on the kernel)
+};
+
+// One wave of the schedule: the leaf blocks of hyperplane k and the update
+// tiles that became ready after hyperplane k-1.  The two run concurrently
+// (on two streams): the updates write only blocks of hyperplanes >= k+1.
+struct Wave {
+    int64_t leaf_first = 0, leaf_count = 0;
+    int64_t item_first = 0, item_count = 0;
+    double leaf_flops = 0, leaf_bytes = 0;
+    double upd_flops = 0, upd_bytes = 0;
+};
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct HostProblem {
+    int d_user = 0;              // order given by the caller
+    int D = 3;                   // internal order
+    int64_t n[kMaxD] = {1, 1, 1, 1};
+    int64_t stride[kMaxD] = {0, 0, 0, 0};
+    std::vector<double> T[kMaxD];          // host copies (row-major)
+    std::vector<int32_t> bst[kMaxD];       // block starts
+    int m[kMaxD] = {1, 1, 1, 1};
+    int64_t N = 0;
+};
+
+struct PlanStats {
+    double flops = 0;            // method flops (FMA = 2)
+    double flops_leaf = 0;
+    double flops_update = 0;
+    int64_t waves = 0;
+    int64_t leaves = 0;
+    int64_t tasks = 0;
+    int64_t items = 0;
+    int64_t launches = 0;
+    int bmax[kMaxD] = {0, 0, 0, 0};
+};
+
+// Host-side schedule (built without touching the GPU).
+struct Schedule {
+    int D = 3;
+    std::vector<HostProblem> probs;
+    std::vector<LeafDesc> leaves;
+    std::vector<UpdDesc> tasks;
+    std::vector<WorkItem> items;
+    std::vector<Wave> waves;
+    PlanStats stats;
+    int bmax[kMaxD] = {1, 1, 1, 1};
+    int leaf_lds_bytes = 0;
+};
+
+// Planner entry: problems must have D, n, stride, T filled.  Returns a
+// status and a message.
+int build_schedule(Schedule& s, int nmin, std::string& err);
+int leaf_lds_bytes(int D, const int* bmax);
+int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst, std::string& err);
+
+// Kernel launchers (tt_kernels.hip).
+hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count,
+                       const ProbDesc* probs, int* status, const int* bmax, int lds_bytes,
+                       hipStream_t st);
+hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
+                         int64_t count, const ProbDesc* probs, hipStream_t st);
+hipError_t launch_zero_int(int* p, int count, hipStream_t st);
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
+}  // namespace tt

@@ -1,0 +1,334 @@
+// Host planner: leaf-block partition, hyperplane waves and the dyadic update
+// schedule of the recursive triangular solve.
+//
+// Algorithm 2 of the paper splits the largest mode at k ~ n_mu/2 (moving k by
+// one when A_mu(k+1,k) != 0, Sec. 2.1), solves the upper half, updates the
+// lower half with X_2 x_mu A_mu(1:k, k+1:n_mu), and recurses down to blocks of
+// size n_min.  Unrolled, every coefficient entry T_mu[i, j] (j past i's
+// diagonal block) is applied exactly once, either inside a leaf (i and j in
+// the same leaf block) or by the update of the unique split that separates
+// their blocks.  Along each mode those splits form a binary tree over the
+// leaf-block indices: the split with midpoint c (c = 1, 2, 3, ...) separates
+// R0 = [c - s, c) from R1 = [c, c + s) where s is the lowest set bit of c.
+//
+// Any order that solves a block after everything it depends on gives the same
+// X (the solution is unique).  The GPU schedule therefore runs the leaves as
+// hyperplane wavefronts over the block grid (block I depends only on blocks
+// that are larger in one index and equal in the others, all on earlier
+// hyperplanes) and applies each split's update per pencil -- the line of
+// blocks along mode mu through I -- as soon as the block at its midpoint c
+// is solved.  At that moment all of R1 is solved and no block of R0 is, so
+// the update is exactly the one of Algorithm 2, restricted to one pencil.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst, std::string& err) {
+    bst.clear();
+    if (n <= 0) {
+        bst.push_back(0);
+        return TT_OK;
+    }
+    // structure: zero below the first subdiagonal, no two consecutive bumps
+    for (int64_t r = 2; r < n; ++r)
+        for (int64_t c = 0; c + 1 < r; ++c)
+            if (T[r * n + c] != 0.0) {
+                err = "coefficient is not upper quasi-triangular: nonzero entry below the subdiagonal at (" +
+                      std::to_string(r) + "," + std::to_string(c) + ")";
+                return TT_EINVAL;
+            }
+    for (int64_t i = 1; i + 1 < n; ++i)
+        if (T[i * n + i - 1] != 0.0 && T[(i + 1) * n + i] != 0.0) {
+            err = "coefficient is not upper quasi-triangular: consecutive nonzero subdiagonal entries at row " +
+                  std::to_string(i);
+            return TT_EINVAL;
+        }
+    // Near-equal blocks of about b rows; a boundary that would cut a 2x2
+    // block moves down by one row (Algorithm 2: k <- k + 1 when A(k+1,k) != 0).
+    auto cuts_bump = [&](int64_t k) { return k > 0 && k < n && T[k * n + k - 1] != 0.0; };
+    int64_t m = (n + b / 2) / b;
+    if (m < 1) m = 1;
+    bst.push_back(0);
+    for (int64_t k = 1; k < m; ++k) {
+        int64_t pos = (k * n + m / 2) / m;
+        if (cuts_bump(pos)) ++pos;
+        if (pos <= bst.back() || pos >= n) continue;
+        bst.push_back((int32_t)pos);
+    }
+    bst.push_back((int32_t)n);
+    for (size_t i = 0; i + 1 < bst.size(); ++i)
+        if (bst[i + 1] - bst[i] > 32) {
+            err = "leaf block larger than 32 rows; use nmin <= 20";
+            return TT_EINVAL;
+        }
+    return TT_OK;
+}
+
+static inline int lowbit(int c) { return c & (-c); }
+
+int build_schedule(Schedule& s, int nmin, std::string& err) {
+    const int D = s.D;
+    if (nmin <= 0) nmin = (D >= 4) ? 8 : 16;
+    if (nmin < 2) nmin = 2;
+    if (nmin > 20) {
+        err = "nmin must be at most 20";
+        return TT_EINVAL;
+    }
+    for (int mu = 0; mu < kMaxD; ++mu) s.bmax[mu] = 1;
+    s.leaves.clear();
+    s.tasks.clear();
+    s.items.clear();
+    s.waves.clear();
+    s.stats = PlanStats();
+
+    int64_t W = 0;
+    for (auto& p : s.probs) {
+        int64_t N = 1;
+        for (int mu = 0; mu < D; ++mu) N *= p.n[mu];
+        p.N = N;
+        for (int mu = 0; mu < D; ++mu) {
+            int rc = partition_mode(p.n[mu], p.T[mu].data(), nmin, p.bst[mu], err);
+            if (rc) return rc;
+            p.m[mu] = (int)p.bst[mu].size() - 1;
+            if (p.m[mu] > 32767) {
+                err = "too many leaf blocks along one mode";
+                return TT_EINVAL;
+            }
+            for (int b = 0; b < p.m[mu]; ++b)
+                s.bmax[mu] = std::max<int>(s.bmax[mu], p.bst[mu][b + 1] - p.bst[mu][b]);
+        }
+        if (N == 0) continue;
+        int64_t w = 1;
+        for (int mu = 0; mu < D; ++mu) w += p.m[mu] - 1;
+        W = std::max(W, w);
+    }
+
+    // bucket the leaf blocks of every problem by wave
+    std::vector<std::vector<LeafDesc>> waves((size_t)W);
+    for (size_t pi = 0; pi < s.probs.size(); ++pi) {
+        const HostProblem& p = s.probs[pi];
+        if (p.N == 0) continue;
+        int64_t total = 1;
+        for (int mu = 0; mu < D; ++mu) total *= p.m[mu];
+        for (int64_t lin = 0; lin < total; ++lin) {
+            LeafDesc L{};
+            L.prob = (int32_t)pi;
+            int64_t rem = lin, w = 0;
+            for (int mu = D - 1; mu >= 0; --mu) {
+                L.blk[mu] = (int16_t)(rem % p.m[mu]);
+                rem /= p.m[mu];
+                w += p.m[mu] - 1 - L.blk[mu];
+            }
+            for (int mu = D; mu < kMaxD; ++mu) L.blk[mu] = 0;
+            waves[(size_t)w].push_back(L);
+        }
+    }
+
+    // Per (problem, mode, block): whether a tree update has already been
+    // scheduled for it (the first one stores, later ones accumulate).
+    std::vector<std::vector<uint8_t>> received(s.probs.size());
+    for (size_t pi = 0; pi < s.probs.size(); ++pi) {
+        int64_t total = 1;
+        for (int mu = 0; mu < D; ++mu) total *= s.probs[pi].m[mu];
+        received[pi].assign((size_t)(total * D), 0);
+    }
+    auto block_lin = [&](const HostProblem& p, const int* I) {
+        int64_t l = 0;
+        for (int mu = 0; mu < D; ++mu) l = l * p.m[mu] + I[mu];
+        return l;
+    };
+
+    // Tasks triggered after each wave, executed together with the next one.
+    std::vector<std::vector<int32_t>> triggered((size_t)W + 1);
+    double fl_leaf = 0, fl_upd = 0;
+    auto add_task = [&](const HostProblem& p, int pi, const int* I, int mu, int lo, int hi_t, int src_lo,
+                        int src_hi, int64_t trigger_wave) {
+        // targets: blocks [lo, hi_t) along mu; sources: blocks [src_lo, src_hi)
+        if (lo >= hi_t || src_lo >= src_hi) return;
+        UpdDesc t{};
+        t.prob = pi;
+        t.mode = (int16_t)mu;
+        t.r0 = p.bst[mu][lo];
+        t.M = p.bst[mu][hi_t] - t.r0;
+        t.k0 = p.bst[mu][src_lo];
+        t.K = p.bst[mu][src_hi] - t.k0;
+        int64_t xb = 0;
+        int q = 0;
+        int ext[3] = {1, 1, 1};
+        int64_t ostr[3] = {0, 0, 0};
+        for (int nu = 0; nu < D; ++nu) {
+            if (nu == mu) continue;
+            int64_t st = p.bst[nu][I[nu]];
+            xb += st * p.stride[nu];
+            ext[q] = p.bst[nu][I[nu] + 1] - (int32_t)st;
+            ostr[q] = p.stride[nu];
+            ++q;
+        }
+        if (q == 2) {  // slot 2 is the fastest of the other modes
+            ext[2] = ext[1];
+            ostr[2] = ostr[1];
+            ext[1] = ext[0];
+            ostr[1] = ostr[0];
+            ext[0] = 1;
+            ostr[0] = 0;
+        }
+        t.xbase = xb;
+        for (int i = 0; i < 3; ++i) {
+            t.ext[i] = ext[i];
+            t.ostr[i] = ostr[i];
+        }
+        t.P = ext[0] * ext[1] * ext[2];
+        if (t.M <= 0 || t.K <= 0 || t.P <= 0) return;
+        // store or accumulate: uniform over the targets of one task
+        int nrec = 0;
+        int J[kMaxD];
+        for (int nu = 0; nu < D; ++nu) J[nu] = I[nu];
+        for (int b = lo; b < hi_t; ++b) {
+            J[mu] = b;
+            uint8_t& r = received[(size_t)pi][(size_t)(block_lin(p, J) * D + mu)];
+            nrec += r;
+            r = 1;
+        }
+        if (mu > 0 && nrec == 0) t.flags |= 1;
+        if (nrec != 0 && nrec != hi_t - lo) t.flags |= 2;  // inconsistent (checked below)
+        triggered[(size_t)trigger_wave].push_back((int32_t)s.tasks.size());
+        s.tasks.push_back(t);
+    };
+
+    // Leaves per wave and the tree updates they trigger.  Along each mode the
+    // split with midpoint c and half-width s = lowbit(c) >= 2 sends R1 =
+    // [c, c+s) to R0 = [c-s, c); the pair (c-1, c) of adjacent blocks is left
+    // to the leaf of block c-1, which reads block c itself.  The rest is
+    //   (1) targets [c-s, c-1) from sources [c, c+s), ready once c is solved;
+    //   (2) target  c-1        from sources [c+1, c+s), ready once c+1 is.
+    // Both have at least one hyperplane of slack before their targets run.
+    for (int64_t w = 0; w < W; ++w) {
+        for (const LeafDesc& L0 : waves[(size_t)w]) {
+            const HostProblem& p = s.probs[(size_t)L0.prob];
+            int I[kMaxD];
+            for (int mu = 0; mu < D; ++mu) I[mu] = L0.blk[mu];
+            for (int mu = 0; mu < D; ++mu) {
+                const int m = p.m[mu];
+                const int c = I[mu];
+                // type (1): this block is the midpoint c
+                if (c >= 1) {
+                    const int sb = lowbit(c);
+                    if (sb >= 2) add_task(p, L0.prob, I, mu, c - sb, c - 1, c, std::min(c + sb, m), w);
+                }
+                // type (2): this block is c + 1 for the midpoint c = I - 1
+                const int c2 = c - 1;
+                if (c2 >= 1) {
+                    const int sb = lowbit(c2);
+                    if (sb >= 2) add_task(p, L0.prob, I, mu, c2 - 1, c2, c2 + 1, std::min(c2 + sb, m), w);
+                }
+            }
+        }
+    }
+    for (const UpdDesc& t : s.tasks)
+        if (t.flags & 2) {
+            err = "internal: mixed first/accumulated targets in one update";
+            return TT_EINVAL;
+        }
+
+    // Leaf flags: accumulator reads and the adjacent block.
+    for (int64_t w = 0; w < W; ++w) {
+        Wave wv;
+        wv.leaf_first = (int64_t)s.leaves.size();
+        for (LeafDesc L : waves[(size_t)w]) {
+            const HostProblem& p = s.probs[(size_t)L.prob];
+            int I[kMaxD];
+            for (int mu = 0; mu < D; ++mu) I[mu] = L.blk[mu];
+            L.flags = 0;
+            for (int mu = 0; mu < D; ++mu) {
+                if (mu > 0 && received[(size_t)L.prob][(size_t)(block_lin(p, I) * D + mu)]) L.flags |= 1 << mu;
+                if (I[mu] + 1 < p.m[mu]) L.flags |= 1 << (4 + mu);
+            }
+            s.leaves.push_back(L);
+            // algorithmic work: in-block back-substitution + the adjacent blocks
+            int64_t sz[kMaxD], ne = 1;
+            for (int mu = 0; mu < D; ++mu) {
+                sz[mu] = p.bst[mu][I[mu] + 1] - p.bst[mu][I[mu]];
+                ne *= sz[mu];
+            }
+            double lf = 0, lb = 16.0 * (double)ne;
+            for (int mu = 0; mu < D; ++mu) {
+                int64_t st = p.bst[mu][I[mu]], nm = p.n[mu];
+                int64_t bumps = 0;
+                for (int64_t i = st; i + 1 < st + sz[mu]; ++i)
+                    if (p.T[mu][(i + 1) * nm + i] != 0.0) ++bumps;
+                double off = (double)sz[mu] * (double)(sz[mu] - 1) / 2.0 + (double)bumps;
+                lf += 2.0 * off * (double)(ne / sz[mu]);
+                lb += 8.0 * (double)(sz[mu] * sz[mu]);
+                if (L.flags & (1 << mu)) lb += 8.0 * (double)ne;
+                if (L.flags & (1 << (4 + mu))) {
+                    int64_t sa = p.bst[mu][I[mu] + 2] - p.bst[mu][I[mu] + 1];
+                    lf += 2.0 * (double)sz[mu] * (double)sa * (double)(ne / sz[mu]);
+                    lb += 8.0 * (double)(ne / sz[mu]) * (double)sa + 8.0 * (double)(sz[mu] * sa);
+                }
+            }
+            wv.leaf_flops += lf;
+            wv.leaf_bytes += lb;
+            fl_leaf += lf;
+        }
+        wv.leaf_count = (int64_t)s.leaves.size() - wv.leaf_first;
+        // update tiles triggered by the previous wave
+        wv.item_first = (int64_t)s.items.size();
+        if (w >= 1) {
+            for (int32_t tid : triggered[(size_t)(w - 1)]) {
+                const UpdDesc& t = s.tasks[(size_t)tid];
+                const bool right = (t.mode == D - 1);
+                const int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
+                const int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
+                for (int a = 0; a < na; ++a)
+                    for (int b = 0; b < nb; ++b) s.items.push_back(WorkItem{tid, (int16_t)a, (int16_t)b});
+                const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
+                wv.upd_flops += f;
+                fl_upd += f;
+                wv.upd_bytes += 8.0 * (((t.flags & 1) ? 1.0 : 2.0) * (double)t.M * t.P + (double)t.K * t.P +
+                                       (double)t.M * t.K);
+            }
+        }
+        wv.item_count = (int64_t)s.items.size() - wv.item_first;
+        s.waves.push_back(wv);
+    }
+    if (!triggered[(size_t)(W > 0 ? W - 1 : 0)].empty()) {
+        err = "internal: updates triggered by the last wave";
+        return TT_EINVAL;
+    }
+
+    // tuple slots within one hyperplane are packed in 11 bits
+    int emax = 2;
+    for (int mu = 0; mu < D - 1; ++mu) emax *= s.bmax[mu];
+    if (emax > 2047) {
+        err = "leaf block too large for the hyperplane lists; lower nmin";
+        return TT_EINVAL;
+    }
+    if (D == 4)
+        for (int mu = 0; mu < D; ++mu)
+            if (s.bmax[mu] > 16) {
+                err = "order-4 leaf blocks must have at most 16 rows per mode; lower nmin";
+                return TT_EINVAL;
+            }
+    s.leaf_lds_bytes = leaf_lds_bytes(D, s.bmax);
+    if (s.leaf_lds_bytes > 160 * 1024) {
+        err = "leaf block does not fit in LDS; lower nmin";
+        return TT_EINVAL;
+    }
+    s.stats.flops_leaf = fl_leaf;
+    s.stats.flops_update = fl_upd;
+    s.stats.flops = fl_leaf + fl_upd;
+    s.stats.waves = W;
+    s.stats.leaves = (int64_t)s.leaves.size();
+    s.stats.tasks = (int64_t)s.tasks.size();
+    s.stats.items = (int64_t)s.items.size();
+    s.stats.launches = 2 * (int64_t)s.waves.size();
+    for (int mu = 0; mu < kMaxD; ++mu) s.stats.bmax[mu] = s.bmax[mu];
+    return TT_OK;
+}
+
+}  // namespace tt

@@ -1,0 +1,150 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import tt_inputs as ti
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12  # normwise relative error, FP64
+
+
+def tt():
+    import paper_1905_09539_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_solve(T, B, nmin=0):
+    X = tt().solve_tri([dev(t) for t in T], dev(B), nmin=nmin)
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+def test_cfg0_32cube():
+    """d = 3, n = 32, bumps at every 8th position (cut every power-of-two split)."""
+    p = ti.laplace_tri((32, 32, 32), seed=0, bumps="every8")
+    print("case cfg0 32^3 seed 0", flush=True)
+    X = gpu_solve(p["T"], p["B"])
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+
+
+@pytest.mark.parametrize("shape,bumps,seed", [
+    ((40, 33, 47), "random", 1), ((17, 64, 9), "every8", 2), ((1, 1, 1), "none", 3),
+    ((2, 3, 5), "aligned", 4), ((70, 5, 66), "random", 5), ((128, 33, 20), "every8", 6),
+    ((31, 31, 31), "aligned", 7), ((19, 23, 29, 17), "random", 8), ((24, 16, 9, 33), "every8", 9),
+    ((100, 90), "random", 10), ((300,), "every8", 11), ((48, 48, 48), "none", 12),
+])
+def test_random_shapes(shape, bumps, seed):
+    p = ti.laplace_tri(shape, seed=seed, bumps=bumps)
+    print("case", shape, bumps, seed, flush=True)
+    X = gpu_solve(p["T"], p["B"])
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+
+
+@pytest.mark.parametrize("nmin", [2, 3, 5, 8, 20])
+def test_leaf_sizes(nmin):
+    """Any split point with A(k+1,k) = 0 is valid (Sec. 2.1): every leaf size
+    gives the same X."""
+    p = ti.laplace_tri((45, 38, 52), seed=21, bumps="random")
+    print("case nmin", nmin, flush=True)
+    X = gpu_solve(p["T"], p["B"], nmin=nmin)
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+
+
+def test_closed_form_diagonal_full_size():
+    """Diagonal T_mu: X = B / (a1_i + a2_j + a3_k), at n = 512."""
+    n = 512
+    g = np.random.default_rng(3)
+    a = [g.uniform(1, 2, n) for _ in range(3)]
+    B = g.standard_normal((n, n, n))
+    print("case diagonal 512^3", flush=True)
+    X = gpu_solve([np.diag(x) for x in a], B)
+    Xc = B / (a[0][:, None, None] + a[1][None, :, None] + a[2][None, None, :])
+    assert rel(X, Xc) < 1e-15
+
+
+def _corner(p, lo):
+    """The solution on the far corner box [lo_mu, n_mu) depends only on that
+    box: it solves the same equation with the trailing blocks of T."""
+    T = [t[l:, l:] for t, l in zip(p["T"], lo)]
+    B = p["B"][tuple(slice(l, None) for l in lo)]
+    return T, np.ascontiguousarray(B)
+
+
+def test_full_size_512_sampled():
+    """n = 512 with the cfg1 triangular factors: exact corner-box parity with
+    the oracle, plus the residual at sampled elements anywhere in the tensor."""
+    n = 512
+    p = ti.laplace_tri((n, n, n), seed=1, bumps="every8")
+    print("case 512^3 solve", flush=True)
+    X = gpu_solve(p["T"], p["B"])
+    lo = (385, 385, 385)  # bumps start at 7 mod 8, so T[385, 384] == 0
+    for t, l in zip(p["T"], lo):
+        assert t[l, l - 1] == 0.0
+    Tc, Bc = _corner(p, lo)
+    Xo = oracle.lap_solve(Tc, Bc)
+    assert rel(X[tuple(slice(l, None) for l in lo)], Xo) <= TOL
+    # sampled residual r_i = B_i - sum_mu sum_j T_mu[i_mu, j] X[.., j, ..]
+    g = np.random.default_rng(7)
+    idx = g.integers(0, n, size=(2000, 3))
+    T1, T2, T3 = p["T"]
+    res = np.empty(len(idx))
+    scale = np.empty(len(idx))
+    for k, (i, j, l) in enumerate(idx):
+        v = T1[i] @ X[:, j, l] + T2[j] @ X[i, :, l] + T3[l] @ X[i, j, :]
+        res[k] = p["B"][i, j, l] - v
+        scale[k] = (np.abs(T1[i]) @ np.abs(X[:, j, l]) + np.abs(T2[j]) @ np.abs(X[i, :, l])
+                    + np.abs(T3[l]) @ np.abs(X[i, j, :]) + abs(p["B"][i, j, l]))
+    assert np.max(np.abs(res) / scale) < 64 * np.finfo(float).eps
+
+
+def test_singular_reported():
+    T1 = np.diag([1.0, 2.0, 3.0])
+    T2 = np.diag([0.5, -2.0, 4.0])
+    T3 = np.zeros((1, 1))
+    B = np.ones((3, 3, 1))
+    print("case singular", flush=True)
+    with pytest.raises(tt().TTError) as e:
+        gpu_solve([T1, T2, T3], B)
+    assert e.value.code == tt().TT_ESINGULAR
+
+
+def test_invalid_structure_rejected():
+    T = np.triu(np.ones((4, 4)))
+    T[3, 1] = 1.0
+    with pytest.raises(tt().TTError) as e:
+        gpu_solve([T, np.eye(2)], np.ones((4, 2)))
+    assert e.value.code == tt().TT_EINVAL
+
+
+def test_empty_mode():
+    B = np.zeros((0, 5, 4))
+    X = tt().solve_tri([dev(np.eye(0)), dev(np.eye(5)), dev(np.eye(4))], dev(B))
+    torch.cuda.synchronize()
+    assert X.shape == (0, 5, 4)
+
+
+def test_in_place_and_plan_reuse():
+    p = ti.laplace_tri((60, 50, 40), seed=4, bumps="random")
+    T = [dev(t) for t in p["T"]]
+    plan = tt().Plan(T, p["B"].shape)
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    for rep in range(3):
+        Bd = dev(p["B"])
+        plan.solve(Bd, Bd)  # in place
+        plan.status()
+        assert rel(Bd.cpu().numpy(), Xo) <= TOL
+    assert plan.flops == oracle.flops_tri(p["T"], p["B"].shape)

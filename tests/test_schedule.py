@@ -1,0 +1,69 @@
+"""Host logic of the solver library (no GPU): the leaf partition and the
+wave/update schedule.  Every coefficient entry must be applied exactly once
+(the schedule's flop count equals the oracle's F_tri), and replaying the
+schedule must find every dependency satisfied (Sec. 2.1: a block needs all
+blocks after it along each mode; an update needs its sources solved and its
+targets unsolved)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import tt_inputs as ti
+
+tt = pytest.importorskip("paper_1905_09539_amd")
+
+
+def test_library_exports_every_declared_symbol():
+    import os
+    import re
+    L = tt.lib()
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "tt.h")).read()
+    declared = set(re.findall(r"^(?:int|double|const char\*|size_t)\s+(\w+)\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared <= set(tt.SYMBOLS)
+
+
+@pytest.mark.parametrize("shape,bumps", [
+    ((32, 32, 32), "every8"), ((512, 512, 512), "every8"), ((37, 20, 45), "random"),
+    ((96, 96, 96, 96), "every8"), ((1024, 1024, 8, 8), "every8"), ((5, 7, 3), "none"),
+    ((64,), "every8"), ((50, 70), "random"), ((200, 150, 180), "random"), ((33, 47, 190), "aligned"),
+    ((1, 1, 1), "none"), ((768, 40, 3), "every8"), ((19, 23, 29, 17), "random"),
+])
+def test_schedule_complete_and_ordered(shape, bumps):
+    p = ti.laplace_tri(shape, seed=3, bumps=bumps)
+    info = tt.schedule_info(p["T"], shape)
+    assert info["dependency_violation"] == 0
+    assert info["flops"] == oracle.flops_tri(p["T"], shape)
+    assert info["flops"] == info["flops_leaf"] + info["flops_update"]
+
+
+@pytest.mark.parametrize("nmin", [2, 3, 5, 8, 12, 20])
+def test_schedule_any_leaf_size(nmin):
+    shape = (45, 38, 52)
+    p = ti.laplace_tri(shape, seed=5, bumps="random")
+    info = tt.schedule_info(p["T"], shape, nmin=nmin)
+    assert info["dependency_violation"] == 0
+    assert info["flops"] == oracle.flops_tri(p["T"], shape)
+
+
+def test_partition_never_cuts_a_bump():
+    """Split points k always satisfy A(k+1, k) = 0 (Sec. 2.1, Algorithm 2)."""
+    n = 512
+    p = ti.laplace_tri((n, n, n), seed=1, bumps="every8")
+    info = tt.schedule_info(p["T"], (n, n, n))
+    # every 8th row starts a bump, so 16-row blocks must grow to 17
+    assert info["bmax0"] == 17 and info["waves"] == 94
+
+
+def test_schedule_rejects_bad_structure():
+    T = np.triu(np.ones((6, 6)))
+    T[4, 2] = 1.0
+    with pytest.raises(tt.TTError) as e:
+        tt.schedule_info([T, np.eye(3), np.eye(2)], (6, 3, 2))
+    assert e.value.code == tt.TT_EINVAL
+    with pytest.raises(tt.TTError):
+        tt.schedule_info([np.eye(4)] * 3, (4, 4, 4), nmin=64)
