@@ -113,6 +113,7 @@ struct Schedule {
 // status and a message.
 int build_schedule(Schedule& s, int nmin, std::string& err);
 int leaf_lds_bytes(int D, const int* bmax);
+int leaf_pool_doubles(int D, const int* bmax);
 int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst, std::string& err);
 
 // Kernel launchers (tt_kernels.hip).

@@ -7,6 +7,8 @@
 //   upd_kernel    - the right-hand-side update of Algorithm 2,
 //                   B_1 <- B_1 - X_2 x_mu A_mu(1:k, k+1:n_mu), for one pencil,
 //                   on FP64 MFMA (v_mfma_f64_16x16x4f64).
+#include <algorithm>
+
 #include "tt_internal.h"
 
 namespace tt {
@@ -116,7 +118,6 @@ __device__ inline double tuple_coupling(double* const* Ts, const int* sz, const 
     return m;
 }
 
-constexpr int kAdjMax = 32;  // largest leaf block edge (checked by the planner)
 constexpr int kBatch = 8;    // global loads a thread keeps in flight
 
 // ---------------------------------------------------------------------------
@@ -188,24 +189,66 @@ __device__ inline bool tuple_solve8(const double (&Dm)[4][4], double c, double (
     return ok;
 }
 
-// Packed element record of the per-hyperplane lists: local coordinates
-// (5 bits per mode for D = 3, 4 bits for D = 4), bit 24+mu set when the
-// coordinate is the first row of a 2x2 block of mode mu, bit 31 set when the
-// element's tuple is 1x...x1.
+// Packed element record of the per-hyperplane lists:
+//   bits 0-15  local coordinates (5 bits per mode for D = 3, 4 for D = 4)
+//   bits 16-19 index q of the element inside its tuple (last mode = bit 0)
+//   bits 20-22 log2 of the tuple's number of unknowns ne
+//   bits 24-27 bit mu set when the coordinate is the first row of a 2x2 block
 template <int D>
 struct ElemRec {
     static constexpr int kBits = (D == 3) ? 5 : 4;
-    __device__ static inline uint32_t make(const int* c, int first_mask, bool single) {
+    __device__ static inline uint32_t make(const int* c, int q, int lne, int first_mask) {
         uint32_t v = 0;
 #pragma unroll
         for (int mu = 0; mu < D; ++mu) v |= (uint32_t)c[mu] << (kBits * mu);
-        return v | ((uint32_t)first_mask << 24) | (single ? 0x80000000u : 0u);
+        return v | ((uint32_t)q << 16) | ((uint32_t)lne << 20) | ((uint32_t)first_mask << 24);
     }
     __device__ static inline void coords(uint32_t v, int* c) {
 #pragma unroll
         for (int mu = 0; mu < D; ++mu) c[mu] = (v >> (kBits * mu)) & ((1 << kBits) - 1);
     }
+    __device__ static inline int q(uint32_t v) { return (v >> 16) & 15; }
+    __device__ static inline int lne(uint32_t v) { return (v >> 20) & 7; }
+    __device__ static inline int fmask(uint32_t v) { return (v >> 24) & 15; }
 };
+
+// 2x2 blocks (mode order) and diagonal sum of the 1x1 modes of the tuple whose
+// first element has local coordinates a and first-row mask fm.
+template <int D>
+__device__ inline void tuple_blocks(double* const* Ts, const int* sz, const int* a, int fm, double (&Dm)[4][4],
+                                    double& cdiag) {
+    int kb = 0;
+    cdiag = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dm[j][v] = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const double* Tm = Ts[mu] + a[mu] * sz[mu] + a[mu];
+        if ((fm >> mu) & 1) {
+            const double d0 = Tm[0], d1 = Tm[1], d2 = Tm[sz[mu]], d3 = Tm[sz[mu] + 1];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j == kb) {
+                    Dm[j][0] = d0;
+                    Dm[j][1] = d1;
+                    Dm[j][2] = d2;
+                    Dm[j][3] = d3;
+                }
+            ++kb;
+        } else {
+            cdiag += Tm[0];
+        }
+    }
+}
+
+// Slot classes of a hyperplane's element list, in layout order: tuples with
+// 16, 8, 4, 2 unknowns, then 1x..x1 tuples.  Each class region starts at a
+// multiple of its tuple size, so no tuple straddles a 64-lane wavefront.
+__device__ inline int ne_class(int lne) { return 4 - lne; }  // lne 4 -> 0, ..., 0 -> 4
+
+constexpr int kPoolWant = 4096;  // doubles of precomputed tuple inverses per leaf
 
 // ---------------------------------------------------------------------------
 // Leaf kernel.  One workgroup per leaf block B.  On entry X[B] holds the
@@ -214,23 +257,29 @@ struct ElemRec {
 //   1. loads X[B] - sum_mu A_mu[B] and the diagonal blocks T_mu[B, B] to LDS;
 //   2. subtracts the contribution of the next block along each mode
 //      (T_mu[B, B+1] x_mu X[B+1]: the split between two adjacent leaves);
-//   3. runs block back-substitution over the 1x1 / 2x2 diagonal blocks
-//      ("tuples") of the leaf, hyperplane by hyperplane: a tuple depends only
-//      on tuples that are larger in one index, so the tuples of one
-//      hyperplane are independent.  Per hyperplane, phase A gives every
-//      (element, mode) pair to its own thread, which sums T_mu[i, j] X[.., j, ..]
-//      over the rows j past the element's diagonal block; phase B completes
-//      each 1x1x1 tuple with one division by its eigenvalue sum and solves
-//      each larger tuple's small system;
-//   4. stores X[B].
+//   3. partitions each mode into its 1x1 / 2x2 diagonal blocks, lists the
+//      elements of every tuple hyperplane (tuples of 16, 8, 4, 2 unknowns
+//      first, each aligned to its size), and inverts the small systems
+//      M_p = sum_mu I (x) T_mu[p_mu, p_mu] (x) I of the tuples with 4 or 8
+//      unknowns, one column per thread;
+//   4. runs block back-substitution hyperplane by hyperplane: a tuple depends
+//      only on tuples that are larger in one index, so the tuples of one
+//      hyperplane are independent.  Phase A gives every (element, mode) its
+//      own thread for the sum of T_mu[i, j] X[.., j, ..] over the rows j past
+//      the element's diagonal block; phase B gives every element its own
+//      thread, which forms the right-hand sides of its tuple and writes its
+//      unknown: a division by the eigenvalue sum (1 unknown), Cramer's rule
+//      (2 unknowns), a row of the precomputed inverse (4 or 8), or Gaussian
+//      elimination with partial pivoting (16, or when the inverse pool is
+//      full).  A tuple's threads share one wavefront, so they all read the
+//      right-hand sides before any of them writes;
+//   5. stores X[B].
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
     const LeafDesc* __restrict__ leaves, int64_t first, const ProbDesc* __restrict__ probs,
-    int* __restrict__ status, int bm0, int bm1, int bm2, int bm3) {
+    int* __restrict__ status, int bm0, int bm1, int bm2, int bm3, int kPoolMax) {
     extern __shared__ double smem[];
-    constexpr int NEMAX = 1 << D;
-    constexpr int kSlots = (D == 4) ? 2 : 0;  // threads that solve tuples with ne = 16
     const int tid = threadIdx.x;
     const LeafDesc L = leaves[first + blockIdx.x];
     const ProbDesc& P = probs[L.prob];
@@ -254,7 +303,7 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) gbase += (int64_t)st[mu] * gs[mu];
 
-    // ---- LDS carve-up (see leaf_lds_bytes)
+    // ---- LDS carve-up (sizes must match leaf_lds_bytes)
     int cap = 1, psum = 0, emax = 2;
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
@@ -267,24 +316,32 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
     double* Xs = smem;
     double* cursor = Xs + cap;
     double* Ts[D];
-    double* Ta[D];
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         Ts[mu] = cursor;
         cursor += bm[mu] * bm[mu];
     }
-#pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        Ta[mu] = cursor;
-        cursor += bm[mu] * bm[mu];
-    }
+    // the blocks next to the diagonal are only needed before the partial
+    // sums exist, so the two share storage
     double* Pp = cursor;  // D * emax partial sums of one hyperplane
-    cursor += D * emax;
-    double* scratch = cursor;  // kSlots x (NEMAX*NEMAX + NEMAX), order 4 only
-    cursor += kSlots * (NEMAX * NEMAX + NEMAX);
-    uint32_t* elist = reinterpret_cast<uint32_t*>(cursor);  // cap
-    uint16_t* tlist = reinterpret_cast<uint16_t*>(elist + cap);  // cap: slot | (log2 ne << 11)
-    int* icur = reinterpret_cast<int*>(tlist + cap + (cap & 1));
+    double* Ta[D];
+    {
+        double* c2 = cursor;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            Ta[mu] = c2;
+            c2 += bm[mu] * bm[mu];
+        }
+    }
+    int tsum = 0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) tsum += bm[mu] * bm[mu];
+    cursor += max(D * emax, tsum);
+    double* pool = cursor;  // precomputed inverses of tuples with 4 or 8 unknowns
+    cursor += kPoolMax;
+    uint32_t* elist = reinterpret_cast<uint32_t*>(cursor);  // cap element records
+    uint16_t* pslot = reinterpret_cast<uint16_t*>(elist + cap);  // cap: pool offset at a tuple's first slot
+    int* icur = reinterpret_cast<int*>(pslot + cap + (cap & 1));
     int* tstart[D];
     int* tidx[D];
 #pragma unroll
@@ -297,14 +354,14 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
     int* ntup = icur;
     icur += D;
     const int nplanes_max = psum + 1;
-    int* ecnt = icur;  // per hyperplane: count, then fill cursor
-    icur += nplanes_max;
-    int* eoff = icur;
+    int* ccnt = icur;  // per hyperplane and class: tuple count, then fill cursor
+    icur += 5 * nplanes_max;
+    int* cbase = icur;  // per hyperplane and class: first slot of the class region
+    icur += 5 * nplanes_max;
+    int* eoff = icur;  // per hyperplane: first slot; eoff[smax+1] = total
     icur += nplanes_max + 1;
-    int* tcnt = icur;
-    icur += nplanes_max;
-    int* toff = icur;
-    icur += nplanes_max + 1;
+    int* poolcnt = icur;
+    icur += 1;
 
     double* __restrict__ Xg = P.X;
     const double* Ag[D];
@@ -374,50 +431,62 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
             }
         }
     }
-    for (int i = tid; i < nplanes_max; i += kLeafThreads) {
-        ecnt[i] = 0;
-        tcnt[i] = 0;
-    }
+    for (int i = tid; i < 5 * nplanes_max; i += kLeafThreads) ccnt[i] = 0;
+    if (tid == 0) *poolcnt = 0;
     __syncthreads();
 
-    // ---- 2. contributions of the next block along each mode: one thread per
-    // fiber along mu; the fiber of the next block sits in registers and meets
-    // every row of T_mu[B, B+1].
+    // ---- 2. contributions of the next block along each mode on FP64 MFMA:
+    // for every fiber f along mu (the other modes' coordinates),
+    //   Xs[f, l] -= sum_j T_mu[B_l, (B+1)_j] X[B+1][f, j],
+    // i.e. C (sz x F) -= A (sz x sa) * Bx (sa x F): one 16-row tile per 16
+    // rows of the leaf, 16 fibers per MFMA column tile, K in steps of 4.
+    {
+        const int lane = tid & 63, wave = tid >> 6;
+        const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        if (sa[mu] == 0) continue;
-        const int ncol = ne_all / sz[mu];
-        const int64_t smu = gs[mu];
-        for (int col = tid; col < ncol; col += kLeafThreads) {
-            int64_t gb = gbase + (int64_t)sz[mu] * smu;
-            int lb = 0, rem = col;
+        for (int mu = 0; mu < D; ++mu) {
+            if (sa[mu] == 0) continue;
+            const int nf = ne_all / sz[mu];
+            const int ntc = (nf + 15) >> 4, ntr = (sz[mu] + 15) >> 4, nks = (sa[mu] + 3) >> 2;
+            const int64_t smu = gs[mu];
+            for (int tile = wave; tile < ntc * ntr; tile += kLeafThreads / 64) {
+                const int tc = tile % ntc, tr = tile / ntc;
+                // this lane's fiber (MFMA column) and its offsets
+                const int f = tc * 16 + li;
+                int lb = 0;
+                int64_t gb = gbase + (int64_t)sz[mu] * smu;
+                {
+                    int rem = (f < nf) ? f : 0;
 #pragma unroll
-            for (int nu = D - 1; nu >= 0; --nu) {
-                if (nu == mu) continue;
-                const int l = rem % sz[nu];
-                rem /= sz[nu];
-                lb += l * ls[nu];
-                gb += (int64_t)l * gs[nu];
-            }
-            double xa[kAdjMax];
-#pragma unroll
-            for (int j = 0; j < kAdjMax; ++j) xa[j] = (j < sa[mu]) ? Xg[gb + j * smu] : 0.0;
-            for (int l = 0; l < sz[mu]; ++l) {
-                const double* Tr = Ta[mu] + l * sa[mu];
-                double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-                for (int j = 0; j < kAdjMax; j += 2) {
-                    if (j < sa[mu]) acc0 = fma(Tr[j], xa[j], acc0);
-                    if (j + 1 < sa[mu]) acc1 = fma(Tr[j + 1], xa[j + 1], acc1);
+                    for (int nu = D - 1; nu >= 0; --nu) {
+                        if (nu == mu) continue;
+                        const int l = rem % sz[nu];
+                        rem /= sz[nu];
+                        lb += l * ls[nu];
+                        gb += (int64_t)l * gs[nu];
+                    }
                 }
-                Xs[lb + l * ls[mu]] -= acc0 + acc1;
+                const int arow = tr * 16 + li;
+                dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < nks; ++ks) {
+                    const int kk = ks * 4 + lk;
+                    const double av = (arow < sz[mu] && kk < sa[mu]) ? Ta[mu][arow * sa[mu] + kk] : 0.0;
+                    const double bv = (f < nf && kk < sa[mu]) ? Xg[gb + kk * smu] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+                if (f < nf) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = tr * 16 + 4 * v + lk;
+                        if (row < sz[mu]) Xs[lb + row * ls[mu]] -= acc[v];
+                    }
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
-    // ---- tuple partition of each mode: tstart (first row of each diagonal
-    // block), tidx (block index of each row)
+    // ---- 3a. tuple partition of each mode
     if (tid < D) {
         const int mu = tid;
         int k = 0, i = 0;
@@ -441,13 +510,11 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
         nt[mu] = ntup[mu];
         smax += nt[mu] - 1;
     }
-    int lead = 1;  // tuples of the leading D-1 modes: one thread each
+    int lead = 1;
 #pragma unroll
     for (int mu = 0; mu < D - 1; ++mu) lead *= nt[mu];
 
-    // ---- per-hyperplane lists.  Every tuple reserves ne consecutive slots of
-    // its hyperplane's element list; tuples with ne > 1 are also listed with
-    // their base slot.
+    // ---- 3b. per-hyperplane element lists, ordered by tuple class
     for (int pass = 0; pass < 2; ++pass) {
         for (int lin = tid; lin < lead; lin += kLeafThreads) {
             int p[D];
@@ -458,23 +525,23 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
                 rem /= nt[mu];
                 plane0 += p[mu];
             }
-            int a[D], w[D], nel = 1;
+            int a[D], w[D], lne0 = 0;
 #pragma unroll
             for (int mu = 0; mu < D - 1; ++mu) {
                 a[mu] = tstart[mu][p[mu]];
                 w[mu] = tstart[mu][p[mu] + 1] - a[mu];
-                nel *= w[mu];
+                lne0 += w[mu] - 1;
             }
             for (int pl = 0; pl < nt[D - 1]; ++pl) {
                 a[D - 1] = tstart[D - 1][pl];
                 w[D - 1] = tstart[D - 1][pl + 1] - a[D - 1];
-                const int ne = nel * w[D - 1];
+                const int lne = lne0 + w[D - 1] - 1, ne = 1 << lne;
                 const int plane = plane0 + pl;
+                const int cls = ne_class(lne);
                 if (pass == 0) {
-                    atomicAdd(&ecnt[plane], ne);
-                    if (ne > 1) atomicAdd(&tcnt[plane], 1);
+                    atomicAdd(&ccnt[plane * 5 + cls], 1);
                 } else {
-                    const int base = atomicAdd(&ecnt[plane], ne);
+                    const int base = cbase[plane * 5 + cls] + atomicAdd(&ccnt[plane * 5 + cls], 1) * ne;
                     int fm = 0;
 #pragma unroll
                     for (int mu = 0; mu < D; ++mu)
@@ -483,41 +550,100 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
                         int c[D], rq = q;
 #pragma unroll
                         for (int mu = D - 1; mu >= 0; --mu) {
-                            const int d = (w[mu] == 2) ? (rq & 1) : 0;
+                            const int dd = (w[mu] == 2) ? (rq & 1) : 0;
                             if (w[mu] == 2) rq >>= 1;
-                            c[mu] = a[mu] + d;
+                            c[mu] = a[mu] + dd;
                         }
                         int first_mask = 0;
 #pragma unroll
                         for (int mu = 0; mu < D; ++mu)
-                            if ((fm >> mu) & 1 && c[mu] == a[mu]) first_mask |= 1 << mu;
-                        elist[base + q] = ElemRec<D>::make(c, first_mask, ne == 1);
+                            if (((fm >> mu) & 1) && c[mu] == a[mu]) first_mask |= 1 << mu;
+                        elist[base + q] = ElemRec<D>::make(c, q, lne, first_mask);
                     }
-                    // slot relative to the start of the hyperplane's list
-                    if (ne > 1)
-                        tlist[atomicAdd(&tcnt[plane], 1)] =
-                            (uint16_t)((base - eoff[plane]) | ((31 - __builtin_clz((unsigned)ne)) << 11));
+                    if (ne == 4 || ne == 8) {
+                        const int po = atomicAdd(poolcnt, ne * ne);
+                        pslot[base] = (po + ne * ne <= kPoolMax) ? (uint16_t)po : (uint16_t)0xffff;
+                    }
                 }
             }
         }
         __syncthreads();
-        if (pass == 0 && tid == 0) {
-            int ea = 0, ta = 0;
-            for (int i = 0; i <= smax; ++i) {
-                eoff[i] = ea;
-                ea += ecnt[i];
-                ecnt[i] = eoff[i];
-                toff[i] = ta;
-                ta += tcnt[i];
-                tcnt[i] = toff[i];
+        if (pass == 0 && tid < 64) {
+            // slot offsets: one lane per hyperplane chunk of 64 (wave scan)
+            int carry = 0;
+            for (int c0 = 0; c0 <= smax; c0 += 64) {
+                const int pl = c0 + tid;
+                int tot = 0;
+                if (pl <= smax) {
+                    int off = 0;
+#pragma unroll
+                    for (int cls = 0; cls < 5; ++cls) {
+                        const int ne = 1 << (4 - cls);
+                        cbase[pl * 5 + cls] = off;  // relative for now
+                        off += ccnt[pl * 5 + cls] * ne;
+                    }
+                    tot = off;
+                }
+                int incl = tot;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int y = __shfl_up(incl, d, 64);
+                    if (tid >= d) incl += y;
+                }
+                if (pl <= smax) {
+                    const int start = carry + incl - tot;
+                    eoff[pl] = start;
+#pragma unroll
+                    for (int cls = 0; cls < 5; ++cls) {
+                        cbase[pl * 5 + cls] += start;
+                        ccnt[pl * 5 + cls] = 0;
+                    }
+                }
+                carry += __shfl(incl, 63, 64);
             }
-            eoff[smax + 1] = ea;
-            toff[smax + 1] = ta;
+            if (tid == 0) eoff[smax + 1] = carry;
         }
         __syncthreads();
     }
 
-    // ---- 3. hyperplanes
+    // ---- 3c. inverses of the tuple systems with 4 or 8 unknowns: one thread
+    // per (tuple, column); column q solves M x = e_q in registers
+    const int total = eoff[smax + 1];
+    for (int sl = tid; sl < total; sl += kLeafThreads) {
+        const uint32_t rec = elist[sl];
+        const int lne = ElemRec<D>::lne(rec);
+        if (lne != 2 && lne != 3) continue;
+        const int q = ElemRec<D>::q(rec), ne = 1 << lne;
+        const int b0 = sl - q;
+        const int po = pslot[b0];
+        if (po == 0xffff) continue;
+        const uint32_t rec0 = elist[b0];
+        int a[D];
+        ElemRec<D>::coords(rec0, a);
+        double Dm[4][4], cdiag;
+        tuple_blocks<D>(Ts, sz, a, ElemRec<D>::fmask(rec0), Dm, cdiag);
+        bool tok;
+        if (ne == 4) {
+            double M[4][4], r4[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) r4[i] = (i == q) ? 1.0 : 0.0;
+            tuple_matrix<4>(M, Dm, cdiag);
+            tok = gepp_small<4>(M, r4, 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pool[po + i * 4 + q] = r4[i];
+        } else {
+            double r8[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) r8[i] = (i == q) ? 1.0 : 0.0;
+            tok = tuple_solve8(Dm, cdiag, r8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) pool[po + i * 8 + q] = r8[i];
+        }
+        if (!tok) atomicOr(status, 1);
+    }
+    __syncthreads();
+
+    // ---- 4. hyperplanes
     bool ok = true;
     for (int s = smax; s >= 0; --s) {
         const int e0 = eoff[s], nel = eoff[s + 1] - e0;
@@ -531,181 +657,146 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
 #pragma unroll
             for (int nu = 0; nu < D; ++nu) e += c[nu] * ls[nu];
             const int i = c[mu];
-            const int js = i + 1 + ((rec >> (24 + mu)) & 1);
+            const int js = i + 1 + ((ElemRec<D>::fmask(rec) >> mu) & 1);
             const int len = sz[mu] - js;
-            const double* Tr = Ts[mu] + i * sz[mu] + js;
-            const double* Xp = Xs + e + (js - i) * ls[mu];
-            const int step = ls[mu];
-            double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-            int k = 0;
-            for (; k + 3 < len; k += 4) {
-                acc0 = fma(Tr[k], Xp[k * step], acc0);
-                acc1 = fma(Tr[k + 1], Xp[(k + 1) * step], acc1);
-                acc2 = fma(Tr[k + 2], Xp[(k + 2) * step], acc2);
-                acc3 = fma(Tr[k + 3], Xp[(k + 3) * step], acc3);
+            double acc0 = 0.0, acc1 = 0.0;
+            if (len > 0) {
+                const double* Tr = Ts[mu] + i * sz[mu] + js;
+                const double* Xp = Xs + e + (js - i) * ls[mu];
+                const int step = ls[mu];
+                for (int k0 = 0; k0 < len; k0 += 16) {
+                    double tv[16], xv[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int k = min(k0 + u, len - 1);
+                        tv[u] = Tr[k];
+                        xv[u] = Xp[k * step];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 16; u += 2) {
+                        if (k0 + u < len) acc0 = fma(tv[u], xv[u], acc0);
+                        if (k0 + u + 1 < len) acc1 = fma(tv[u + 1], xv[u + 1], acc1);
+                    }
+                }
             }
-            for (; k < len; ++k) acc0 = fma(Tr[k], Xp[k * step], acc0);
-            Pp[it] = (acc0 + acc1) + (acc2 + acc3);
+            Pp[it] = acc0 + acc1;
         }
         __syncthreads();
-        // phase B: 1x1x1 tuples (one thread per element, from the bottom) and
-        // larger tuples (one thread per tuple, from the top)
+        // phase B: one thread per element of the hyperplane
         for (int j = tid; j < nel; j += kLeafThreads) {
             const uint32_t rec = elist[e0 + j];
-            if (!(rec >> 31)) continue;
+            const int lne = ElemRec<D>::lne(rec), q = ElemRec<D>::q(rec);
             int c[D];
             ElemRec<D>::coords(rec, c);
             int e = 0;
-            double dg = 0.0, r = 0.0;
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) {
-                e += c[mu] * ls[mu];
-                dg += Ts[mu][c[mu] * sz[mu] + c[mu]];
-                r += Pp[D * j + mu];
-            }
-            const double x = (Xs[e] - r) / dg;
-            if (dg == 0.0 || !isfinite(x)) ok = false;
-            Xs[e] = x;
-        }
-        const int t0 = toff[s], ntu = toff[s + 1] - t0;
-        for (int ti = kLeafThreads - 1 - tid; ti < ntu; ti += kLeafThreads) {
-            const uint32_t tr = tlist[t0 + ti];
-            const int base = tr & 0x7ff, ne = 1 << (tr >> 11);
-            const uint32_t rec0 = elist[e0 + base];
-            int a[D], w[D];
-            ElemRec<D>::coords(rec0, a);  // first element = lowest coordinates
-            int eb = 0, kb = 0;
-            double cdiag = 0.0;
-            double Dm[4][4];
+            for (int mu = 0; mu < D; ++mu) e += c[mu] * ls[mu];
+            double x;
+            if (lne == 0) {
+                double dg = 0.0, r = Xs[e];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) Dm[j][v] = 0.0;
-#pragma unroll
-            for (int mu = 0; mu < D; ++mu) {
-                w[mu] = ((rec0 >> (24 + mu)) & 1) ? 2 : 1;
-                eb += a[mu] * ls[mu];
-                const double* Tm = Ts[mu] + a[mu] * sz[mu] + a[mu];
-                if (w[mu] == 2) {
-                    const double d0 = Tm[0], d1 = Tm[1], d2 = Tm[sz[mu]], d3 = Tm[sz[mu] + 1];
-                    // compact the 2x2 blocks in mode order (static indices only)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (j == kb) {
-                            Dm[j][0] = d0;
-                            Dm[j][1] = d1;
-                            Dm[j][2] = d2;
-                            Dm[j][3] = d3;
-                        }
-                    ++kb;
-                } else {
-                    cdiag += Tm[0];
+                for (int mu = 0; mu < D; ++mu) {
+                    dg += Ts[mu][c[mu] * sz[mu] + c[mu]];
+                    r -= Pp[D * j + mu];
                 }
-            }
-            // right-hand sides in local order (last mode fastest = bit 0)
-            double rb[8];
-            int eidx[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                eidx[q] = eb;
-                rb[q] = 0.0;
-                if (q < ne) {
-                    int rq = q, e = eb;
-#pragma unroll
-                    for (int mu = D - 1; mu >= 0; --mu)
-                        if (w[mu] == 2) {
-                            e += (rq & 1) * ls[mu];
-                            rq >>= 1;
-                        }
-                    eidx[q] = e;
-                    double r = Xs[e];
-#pragma unroll
-                    for (int mu = 0; mu < D; ++mu) r -= Pp[D * (base + q) + mu];
-                    rb[q] = r;
-                }
-            }
-            bool tok = true;
-            if (ne == 2) {
-                double M[2][2], r2[2] = {rb[0], rb[1]};
-                tuple_matrix<2>(M, Dm, cdiag);
-                tok = gepp_small<2>(M, r2, 2);
-                rb[0] = r2[0];
-                rb[1] = r2[1];
-            } else if (ne == 4) {
-                double M[4][4], r4[4] = {rb[0], rb[1], rb[2], rb[3]};
-                tuple_matrix<4>(M, Dm, cdiag);
-                tok = gepp_small<4>(M, r4, 4);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) rb[q] = r4[q];
-            } else if (ne == 8) {
-                tok = tuple_solve8(Dm, cdiag, rb);
+                x = r / dg;
+                if (dg == 0.0 || !isfinite(x)) ok = false;
             } else {
-                tok = false;  // ne = 16 is handled below
-            }
-            if (ne <= 8) {
-                if (!tok) ok = false;
+                const int ne = 1 << lne, b0 = j - q;
+                const uint32_t rec0 = elist[e0 + b0];
+                int a[D];
+                ElemRec<D>::coords(rec0, a);
+                const int fm = ElemRec<D>::fmask(rec0);
+                // right-hand sides of the whole tuple (last bumped mode = bit 0)
+                constexpr int NEM = 1 << D;
+                double rb[NEM];
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (q < ne) Xs[eidx[q]] = rb[q];
-            }
-        }
-        if (D == 4) {
-            // ne = 16 (2x2 blocks in all four modes): staged in LDS
-            if (tid < kSlots) {
-                double* Ms = scratch + tid * (NEMAX * NEMAX + NEMAX);
-                double* rs = Ms + NEMAX * NEMAX;
-                for (int ti = tid; ti < ntu; ti += kSlots) {
-                    const uint32_t tr = tlist[t0 + ti];
-                    const int base = tr & 0x7ff, ne = 1 << (tr >> 11);
-                    if (ne != 16) continue;
-                    const uint32_t rec0 = elist[e0 + base];
-                    int a[D], w[D];
-                    ElemRec<D>::coords(rec0, a);
+                for (int qq = 0; qq < NEM; ++qq) {
+                    rb[qq] = 0.0;
+                    if (qq < ne) {
+                        int rq = qq, eq = 0;
 #pragma unroll
-                    for (int mu = 0; mu < D; ++mu) w[mu] = 2;
-                    for (int q = 0; q < ne; ++q) {
-                        double r = Xs[tuple_elem<D>(ls, a, w, q)];
-                        for (int mu = 0; mu < D; ++mu) r -= Pp[D * (base + q) + mu];
-                        rs[q] = r;
-                        for (int q2 = 0; q2 < ne; ++q2) Ms[q * ne + q2] = tuple_coupling<D>(Ts, sz, a, w, q, q2);
-                    }
-                    for (int k = 0; k < ne; ++k) {
-                        int piv = k;
-                        for (int i2 = k + 1; i2 < ne; ++i2)
-                            if (fabs(Ms[i2 * ne + k]) > fabs(Ms[piv * ne + k])) piv = i2;
-                        if (piv != k) {
-                            for (int j = 0; j < ne; ++j) {
-                                double t = Ms[k * ne + j];
-                                Ms[k * ne + j] = Ms[piv * ne + j];
-                                Ms[piv * ne + j] = t;
+                        for (int mu = D - 1; mu >= 0; --mu) {
+                            int dd = 0;
+                            if ((fm >> mu) & 1) {
+                                dd = rq & 1;
+                                rq >>= 1;
                             }
-                            double t = rs[k];
-                            rs[k] = rs[piv];
-                            rs[piv] = t;
+                            eq += (a[mu] + dd) * ls[mu];
                         }
-                        const double pv = Ms[k * ne + k];
-                        if (pv == 0.0) ok = false;
-                        for (int i2 = k + 1; i2 < ne; ++i2) {
-                            const double f = Ms[i2 * ne + k] / pv;
-                            for (int j = k; j < ne; ++j) Ms[i2 * ne + j] -= f * Ms[k * ne + j];
-                            rs[i2] -= f * rs[k];
-                        }
+                        double r = Xs[eq];
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu) r -= Pp[D * (b0 + qq) + mu];
+                        rb[qq] = r;
                     }
-                    for (int k = ne - 1; k >= 0; --k) {
-                        double acc = rs[k];
-                        for (int j = k + 1; j < ne; ++j) acc -= Ms[k * ne + j] * rs[j];
-                        rs[k] = acc / Ms[k * ne + k];
-                        if (!isfinite(rs[k])) ok = false;
+                }
+                const int po = (ne == 4 || ne == 8) ? (int)pslot[e0 + b0] : 0xffff;
+                if (ne == 2) {
+                    double Dm[4][4], cdiag;
+                    tuple_blocks<D>(Ts, sz, a, fm, Dm, cdiag);
+                    const double m00 = Dm[0][0] + cdiag, m01 = Dm[0][1], m10 = Dm[0][2], m11 = Dm[0][3] + cdiag;
+                    const double det = m00 * m11 - m01 * m10;
+                    x = (q == 0) ? (m11 * rb[0] - m01 * rb[1]) / det : (m00 * rb[1] - m10 * rb[0]) / det;
+                    if (det == 0.0 || !isfinite(x)) ok = false;
+                } else if (po != 0xffff) {
+                    const double* Mi = pool + po + q * ne;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int qq = 0; qq < 8; ++qq)
+                        if (qq < ne) acc = fma(Mi[qq], rb[qq], acc);
+                    x = acc;
+                    if (!isfinite(x)) ok = false;
+                } else if (ne <= 8) {
+                    // inverse pool full: eliminate in registers
+                    double Dm[4][4], cdiag;
+                    tuple_blocks<D>(Ts, sz, a, fm, Dm, cdiag);
+                    if (ne == 4) {
+                        double M[4][4], r4[4] = {rb[0], rb[1], rb[2], rb[3]};
+                        tuple_matrix<4>(M, Dm, cdiag);
+                        if (!gepp_small<4>(M, r4, 4)) ok = false;
+                        x = r4[0];
+#pragma unroll
+                        for (int qq = 1; qq < 4; ++qq)
+                            if (qq == q) x = r4[qq];
+                    } else {
+                        double r8[8];
+#pragma unroll
+                        for (int qq = 0; qq < 8; ++qq) r8[qq] = rb[qq];
+                        if (!tuple_solve8(Dm, cdiag, r8)) ok = false;
+                        x = r8[0];
+#pragma unroll
+                        for (int qq = 1; qq < 8; ++qq)
+                            if (qq == q) x = r8[qq];
                     }
-                    for (int q = 0; q < ne; ++q) Xs[tuple_elem<D>(ls, a, w, q)] = rs[q];
+                } else {
+                    x = 0.0;
+                    if constexpr (D == 4) {
+                        // 16 unknowns (2x2 blocks in every mode; rare)
+                        double M[16][16];
+                        int w[D];
+#pragma unroll
+                        for (int mu = 0; mu < D; ++mu) w[mu] = 2;
+#pragma unroll
+                        for (int q1 = 0; q1 < 16; ++q1)
+#pragma unroll
+                            for (int q2 = 0; q2 < 16; ++q2) M[q1][q2] = tuple_coupling<D>(Ts, sz, a, w, q1, q2);
+                        if (!gepp_small<16>(M, rb, 16)) ok = false;
+                        x = rb[0];
+#pragma unroll
+                        for (int qq = 1; qq < 16; ++qq)
+                            if (qq == q) x = rb[qq];
+                    }
                 }
             }
+            // every thread of this wavefront has read its right-hand sides
+            // (program order within a wavefront) before any writes below
+            Xs[e] = x;
         }
         __syncthreads();
     }
     if (!ok) atomicOr(status, 1);
 
-    // ---- 4. store the solved block
+    // ---- 5. store the solved block
     for (int base = 0; base < ne_all; base += kLeafThreads * kBatch) {
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -715,22 +806,31 @@ __global__ __launch_bounds__(kLeafThreads) void leaf_kernel(
     }
 }
 
-int leaf_lds_bytes(int D, const int* bmax) {
+// LDS bytes of the leaf kernel without the inverse pool; the pool gets what
+// is left of the 160 KB (up to kPoolWant doubles).
+static int leaf_lds_base_bytes(int D, const int* bmax) {
     int cap = 1, tsum = 0, isum = 0, psum = 0, emax = 2;
     for (int mu = 0; mu < D; ++mu) {
         cap *= bmax[mu];
-        tsum += 2 * bmax[mu] * bmax[mu];
+        tsum += bmax[mu] * bmax[mu];
         isum += 2 * bmax[mu] + 1;
         psum += bmax[mu];
     }
     for (int mu = 0; mu < D - 1; ++mu) emax *= bmax[mu];
     if (emax > cap) emax = cap;
-    const int nemax = 1 << D;
-    const int slots = (D == 4) ? 2 : 0;
-    const int dbl = cap + tsum + D * emax + slots * (nemax * nemax + nemax);
-    const int ints = isum + D + 4 * (psum + 1) + 2;
+    const int dbl = cap + tsum + std::max(D * emax, tsum);
+    const int ints = isum + D + 11 * (psum + 1) + 2;
     return dbl * (int)sizeof(double) + cap * (int)sizeof(uint32_t) + (cap + (cap & 1)) * (int)sizeof(uint16_t) +
            ints * (int)sizeof(int);
+}
+
+int leaf_pool_doubles(int D, const int* bmax) {
+    const int room = (160 * 1024 - leaf_lds_base_bytes(D, bmax)) / (int)sizeof(double);
+    return std::max(0, std::min(kPoolWant, room));
+}
+
+int leaf_lds_bytes(int D, const int* bmax) {
+    return leaf_lds_base_bytes(D, bmax) + leaf_pool_doubles(D, bmax) * (int)sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -947,10 +1047,10 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     }
     if (D == 3) {
         hipLaunchKernelGGL(leaf_kernel<3>, grid, block, lds_bytes, st, leaves, first, probs, status,
-                           bmax[0], bmax[1], bmax[2], 1);
+                           bmax[0], bmax[1], bmax[2], 1, leaf_pool_doubles(3, bmax));
     } else {
         hipLaunchKernelGGL(leaf_kernel<4>, grid, block, lds_bytes, st, leaves, first, probs, status,
-                           bmax[0], bmax[1], bmax[2], bmax[3]);
+                           bmax[0], bmax[1], bmax[2], bmax[3], leaf_pool_doubles(4, bmax));
     }
     return hipGetLastError();
 }
