@@ -84,12 +84,20 @@ const char* tt_last_error(void);
  * merging of small modes).
  *   T[mu]: upper quasi-triangular coefficients A_mu (device).
  *   C:     NULL for the Laplace-like form, else a host array of d device
- *          pointers to UPPER TRIANGULAR C_mu (pair form).
+ *          pointers to UPPER TRIANGULAR C_mu with nonzero diagonal (pair
+ *          form).  The pair operator equals the Laplace-like operator of
+ *          T'_mu = C_mu^{-1} A_mu followed by x_1 C_1 ... x_d C_d (products
+ *          in different modes commute), so the pair form is solved as
+ *          X = L(T')^{-1}(B x_1 C_1^{-1} ... x_d C_d^{-1}); T'_mu and C_mu^{-1}
+ *          are formed on the host, the products run on the GPU.
  *   B:     right-hand side (device, read only unless X == B).
- *   X:     solution (device); X may alias B.
+ *   X:     solution (device); X may alias B (FP64 only).
+ *   opts->prec: TT_MP_FP32 (Laplace-like form only) solves with FP32-MFMA
+ *          recursion updates and refines in FP64 with the residual
+ *          B - sum_mu X x_mu T_mu; X must not alias B.
  * Errors: TT_EINVAL (d, n, NULL pointer, T not quasi-triangular, C not
  * triangular), TT_ESINGULAR (zero pivot or non-finite result; X content is
- * then unspecified), TT_ENOMEM, TT_EHIP.
+ * then unspecified), TT_ENOTCONV, TT_ENOMEM, TT_EHIP.
  * ------------------------------------------------------------------------- */
 int solve_tri_tensor(int d, const int64_t* n, const double* const* T,
                      const double* const* C, const double* B, double* X,
@@ -102,9 +110,12 @@ int solve_tri_tensor(int d, const int64_t* n, const double* const* T,
  * GPU, the triangular solve, and X = X~ x_1 U_1 ... x_d U_d on the GPU.
  *   A_host[mu]: HOST pointers to dense row-major n[mu] x n[mu] matrices.
  *   B, X: device tensors; X may alias B.
- * opts->prec selects FP64 or mixed precision with FP64 iterative refinement
- * (residual B - sum_mu X x_mu A_mu always in FP64); opts->info[0..1] report
- * the iterations and the last correction ratio.
+ * opts->prec selects FP64 or TT_MP_FP32: transforms and recursion updates in
+ * FP32 MFMA with FP32 accumulation, leaf solves (with their divisions by
+ * eigenvalue sums) in FP64, and FP64 iterative refinement with the residual
+ * B - sum_mu X x_mu A_mu of the dense A_mu (X must not alias B then).
+ * opts->info[0..2] report the refinement iterations, the last ratio
+ * ||D||_F/||X||_F and the host seconds (Schur + planning).
  * Errors: as solve_tri_tensor, plus TT_EINVAL if the QR iteration does not
  * converge, TT_ENOTCONV if refinement stops above opts->tol.
  * ------------------------------------------------------------------------- */
@@ -122,6 +133,8 @@ int solve_general_tensor(int d, const int64_t* n, const double* const* A_host,
  *   X: the forward solution (device).  dB: device tensor (may alias G).
  *   dT: host array of d device pointers to n[mu] x n[mu] outputs, or NULL to
  *       skip the coefficient gradients; individual entries may be NULL.
+ *   The adjoint system is solved by the same kernels in reversed index
+ *   order; dT is a split-K FP64-MFMA product (workspace allocated inside).
  * Errors: as solve_tri_tensor.
  * ------------------------------------------------------------------------- */
 int solve_backward(int d, const int64_t* n, const double* const* T,
@@ -154,12 +167,21 @@ int solve_backward_batched(int count, const int* d, const int64_t* const* n,
  *     TT_ESINGULAR if that solve met a zero pivot or a non-finite value.
  *   tt_plan_flops  returns the method's flop count (one FMA = 2 flops):
  *     2 * sum_mu (n_mu (n_mu - 1) / 2 + bumps_mu) * N / n_mu for the
- *     Laplace-like form.
+ *     Laplace-like form, plus 2 n_mu N per mode product of the pair form
+ *     (d products) and of the dense-coefficient pipeline (2d products).
+ *   Batched and adjoint plans are FP64 only; tt_plan_create with
+ *     opts->prec = TT_MP_FP32 (Laplace-like form) refines in FP64.
  * ------------------------------------------------------------------------- */
 typedef struct tt_plan_s* tt_plan;
 
 int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T,
                    const double* const* C, int trans, const tt_opts* opts);
+/* Dense coefficients (Algorithm 1): the host Schur decompositions happen
+ * here; tt_plan_solve then runs B x_mu U_mu^T, the triangular solve and
+ * x_mu U_mu on the GPU (and the refinement loop when opts->prec is
+ * TT_MP_FP32).  A_host: HOST pointers to row-major n[mu] x n[mu] matrices. */
+int tt_plan_create_general(tt_plan* out, int d, const int64_t* n,
+                           const double* const* A_host, const tt_opts* opts);
 int tt_plan_create_batched(tt_plan* out, int count, const int* d,
                            const int64_t* const* n, const double* const* const* T,
                            int trans, const tt_opts* opts);
@@ -175,7 +197,26 @@ int tt_plan_status(tt_plan plan);
  * end of the last one. */
 int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, double* out);
 double tt_plan_flops(tt_plan plan);
+/* out[4]: [0] refinement iterations of the last solve, [1] its last
+ * ||D||_F/||X||_F, [2] plan build seconds (host), [3] host Schur seconds. */
+int tt_plan_info(tt_plan plan, double* out);
 int tt_plan_destroy(tt_plan plan);
+
+/* Host-only schedule query (no GPU): plans the triangular solve of one
+ * problem with HOST coefficients T_host[mu] (row-major) and leaf edge nmin,
+ * and fills out[13]: flops, leaf flops, update flops, waves, leaves, update
+ * tasks, update tiles, kernel launches, the largest leaf edge per internal
+ * mode (4 entries), and a dependency check of the schedule (0 = every update
+ * reads only solved blocks and every leaf has all its contributions).
+ * Errors: as tt_plan_create. */
+int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int nmin, double* out);
+
+/* Host-only real Schur decomposition A = U T U^T of Algorithm 1 (Householder
+ * Hessenberg reduction, Francis double-shift QR, standardised 2x2 blocks:
+ * equal diagonal entries, off-diagonal entries of opposite sign).  A, T, U:
+ * HOST row-major n x n arrays (A is not modified).  No GPU is used.
+ * Errors: TT_EINVAL (bad arguments, non-finite entries, no convergence). */
+int tt_schur_host(int n, const double* A, double* T, double* U);
 
 #ifdef __cplusplus
 }

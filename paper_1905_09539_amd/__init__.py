@@ -43,7 +43,7 @@ SYMBOLS = [
     "solve_general_tensor", "solve_backward", "solve_tri_tensor_batched",
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
-    "tt_schedule_info", "tt_plan_profile",
+    "tt_schedule_info", "tt_plan_profile", "tt_plan_create_general", "tt_plan_info", "tt_schur_host",
 ]
 
 
@@ -76,6 +76,9 @@ def lib():
         L.tt_plan_destroy.argtypes = [vp]
         L.tt_plan_profile.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
         L.tt_schedule_info.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.tt_plan_create_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, ctypes.POINTER(Opts)]
+        L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.tt_schur_host.argtypes = [ctypes.c_int, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -114,32 +117,119 @@ def _opts(nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None):
     return o
 
 
-def solve_tri(T, B, C=None, X=None, nmin=0, stream=None):
+def solve_tri(T, B, C=None, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None):
     """Solve sum_mu X x_mu T_mu = B (Laplace-like form, eq. (2.2)) or, with
     C given, the pair form sum_mu X x_1 C_1 .. x_mu T_mu .. x_d C_d = B.
     T, C: lists of n_mu x n_mu float64 CUDA tensors (T upper quasi-triangular,
-    C upper triangular); B: float64 CUDA tensor of shape (n_1, ..., n_d)."""
+    C upper triangular); B: float64 CUDA tensor of shape (n_1, ..., n_d).
+    prec=TT_MP_FP32: FP32-MFMA updates with FP64 refinement (info, if a dict,
+    receives iterations and the last correction ratio)."""
     import torch
     if X is None:
         X = torch.empty_like(B)
     tp = _ptr_array([_dev(t) for t in T])
     cp = _ptr_array([_dev(c) for c in C]) if C is not None else None
-    o = _opts(nmin=nmin, stream=stream)
-    _check(lib().solve_tri_tensor(B.dim(), _shape(B.shape), tp, cp, _dev(B), _dev(X), ctypes.byref(o)))
+    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream)
+    rc = lib().solve_tri_tensor(B.dim(), _shape(B.shape), tp, cp, _dev(B), _dev(X), ctypes.byref(o))
+    if info is not None:
+        info.update(iterations=int(o.info[0]), ratio=o.info[1], host_seconds=o.info[2])
+    _check(rc)
     return X
 
 
-class Plan:
-    """A reusable schedule for solving with fixed coefficients (tt_plan_*)."""
+def _host_mats(A):
+    mats = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in A]
+    return mats, _ptr_array([m.ctypes.data for m in mats])
 
-    def __init__(self, T, shape=None, nmin=0, trans=False, batch_T=None, batch_shapes=None):
+
+def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None):
+    """Algorithm 1: solve sum_mu X x_mu A_mu = B for dense A_mu given as HOST
+    (numpy) n_mu x n_mu arrays; B: float64 CUDA tensor.  Host Schur, then
+    transforms and the triangular solve on the GPU."""
+    import torch
+    if X is None:
+        X = torch.empty_like(B)
+    mats, ap = _host_mats(A)
+    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream)
+    rc = lib().solve_general_tensor(B.dim(), _shape(B.shape), ap, _dev(B), _dev(X), ctypes.byref(o))
+    if info is not None:
+        info.update(iterations=int(o.info[0]), ratio=o.info[1], host_seconds=o.info[2])
+    _check(rc)
+    return X
+
+
+def solve_backward(T, X, G, dB=None, grads=True, dense_grad=False, nmin=0, stream=None):
+    """Adjoint of solve_tri for L with dL/dX = G: returns (dB, dT) with
+    dB = Lam solving sum_mu Lam x_mu T_mu^T = G and dT[mu] = -Lam_(mu) X_(mu)^T
+    (masked to the pattern of T[mu] unless dense_grad); dT is None if not grads."""
+    import torch
+    if dB is None:
+        dB = torch.empty_like(G)
+    tp = _ptr_array([_dev(t) for t in T])
+    dT = [torch.empty_like(t) for t in T] if grads else None
+    dtp = _ptr_array([_dev(t) for t in dT]) if grads else None
+    o = _opts(nmin=nmin, stream=stream)
+    _check(lib().solve_backward(G.dim(), _shape(G.shape), tp, ctypes.c_void_p(_dev(X)) if grads else None,
+                                _dev(G), _dev(dB), dtp, int(bool(dense_grad)), ctypes.byref(o)))
+    return dB, dT
+
+
+def solve_backward_batched(T, X, G, grads=True, dense_grad=False, nmin=0, stream=None):
+    """Batched solve_backward over independent problems (lists of per-problem
+    coefficient lists and tensors).  Returns (list of dB, list of dT lists)."""
+    import torch
+    count = len(G)
+    ds = (ctypes.c_int * count)(*[g.dim() for g in G])
+    shp = [_shape(g.shape) for g in G]
+    shp_arr = (ctypes.c_void_p * count)(*[ctypes.cast(x, ctypes.c_void_p).value for x in shp])
+    tarrs = [_ptr_array([_dev(t) for t in Tb]) for Tb in T]
+    t_arr = (ctypes.c_void_p * count)(*[ctypes.cast(a, ctypes.c_void_p).value for a in tarrs])
+    dB = [torch.empty_like(g) for g in G]
+    dT = [[torch.empty_like(t) for t in Tb] for Tb in T] if grads else None
+    dtarrs = [_ptr_array([_dev(t) for t in l]) for l in dT] if grads else None
+    dt_arr = (ctypes.c_void_p * count)(*[ctypes.cast(a, ctypes.c_void_p).value for a in dtarrs]) if grads else None
+    o = _opts(nmin=nmin, stream=stream)
+    _check(lib().solve_backward_batched(count, ds, shp_arr, t_arr, _ptr_array([_dev(x) for x in X]),
+                                        _ptr_array([_dev(g) for g in G]), _ptr_array([_dev(b) for b in dB]),
+                                        dt_arr, int(bool(dense_grad)), ctypes.byref(o)))
+    return dB, dT
+
+
+def schur_host(A):
+    """Host real Schur decomposition A = U T U^T (numpy in, numpy out)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    n = A.shape[0]
+    T = np.zeros_like(A)
+    U = np.zeros_like(A)
+    _check(lib().tt_schur_host(n, A.ctypes.data, T.ctypes.data, U.ctypes.data))
+    return T, U
+
+
+class Plan:
+    """A reusable schedule for solving with fixed coefficients (tt_plan_*).
+    T: device coefficient list (C: optional device list for the pair form);
+    general=True takes T as HOST dense matrices (Algorithm 1 pipeline)."""
+
+    def __init__(self, T, shape=None, nmin=0, trans=False, batch_T=None, batch_shapes=None, C=None,
+                 general=False, prec=TT_FP64, tol=1e-13, max_iter=10):
         self._h = ctypes.c_void_p()
-        o = _opts(nmin=nmin)
-        if batch_T is None:
-            self._keep = [_ptr_array([_dev(t) for t in T])]
+        o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter)
+        if general:
+            mats, ap = _host_mats(T)
+            self._keep = [mats, ap]
             self.count = 1
             self.shapes = [tuple(int(x) for x in shape)]
-            _check(lib().tt_plan_create(ctypes.byref(self._h), len(shape), _shape(shape), self._keep[0], None,
+            _check(lib().tt_plan_create_general(ctypes.byref(self._h), len(shape), _shape(shape), ap,
+                                                ctypes.byref(o)))
+        elif batch_T is None:
+            self._keep = [_ptr_array([_dev(t) for t in T])]
+            cp = None
+            if C is not None:
+                cp = _ptr_array([_dev(c) for c in C])
+                self._keep.append(cp)
+            self.count = 1
+            self.shapes = [tuple(int(x) for x in shape)]
+            _check(lib().tt_plan_create(ctypes.byref(self._h), len(shape), _shape(shape), self._keep[0], cp,
                                         int(bool(trans)), ctypes.byref(o)))
         else:
             self.count = len(batch_T)
@@ -190,6 +280,11 @@ class Plan:
     def status(self):
         _check(lib().tt_plan_status(self._h))
 
+    def info(self):
+        out = (ctypes.c_double * 4)()
+        _check(lib().tt_plan_info(self._h, out))
+        return {"iterations": int(out[0]), "ratio": out[1], "build_seconds": out[2], "schur_seconds": out[3]}
+
     def close(self):
         if self._h:
             lib().tt_plan_destroy(self._h)
@@ -212,3 +307,37 @@ def schedule_info(T_host, shape, nmin=0):
     keys = ["flops", "flops_leaf", "flops_update", "waves", "leaves", "tasks", "items", "launches",
             "bmax0", "bmax1", "bmax2", "bmax3", "dependency_violation"]
     return dict(zip(keys, list(out)))
+
+
+def _autograd_class():
+    import torch
+
+    class TriTensorSolve(torch.autograd.Function):
+        """X = solve_tri(T, B) with gradients: dL/dB = Lam (adjoint solve)
+        and dL/dT_mu = -Lam_(mu) X_(mu)^T masked to the pattern of T_mu.
+        Usage: X = TriTensorSolve.apply(B, T_1, ..., T_d)."""
+
+        @staticmethod
+        def forward(ctx, B, *T):
+            X = solve_tri(list(T), B.contiguous())
+            ctx.save_for_backward(X, *T)
+            return X
+
+        @staticmethod
+        def backward(ctx, G):
+            X, *T = ctx.saved_tensors
+            need_T = any(ctx.needs_input_grad[1:])
+            dB, dT = solve_backward(T, X, G.contiguous(), grads=need_T)
+            if not need_T:
+                dT = [None] * len(T)
+            return (dB,) + tuple(dT)
+
+    return TriTensorSolve
+
+
+def __getattr__(name):
+    if name == "TriTensorSolve":
+        cls = _autograd_class()
+        globals()["TriTensorSolve"] = cls
+        return cls
+    raise AttributeError(name)

@@ -62,10 +62,13 @@ static unsigned grid_for(int64_t n) {
 
 using namespace tt;
 
+enum PlanKind { KIND_TRI = 0, KIND_PAIR = 1, KIND_GENERAL = 2 };
+
 struct tt_plan_s {
     Schedule sched;
     int trans = 0;
     int count = 0;
+    int kind = KIND_TRI;
     std::vector<int> d_user;
     // device
     ProbDesc* d_probs = nullptr;
@@ -79,7 +82,24 @@ struct tt_plan_s {
     hipEvent_t ev_start = nullptr;
     hipStream_t last_stream = nullptr;
     double build_seconds = 0;
+    double schur_seconds = 0;
     int device = 0;
+    // pipelines (pair form, dense coefficients): mode products applied to B
+    // before the triangular solve (pre) and to its result after (post), one
+    // row-major n_mu x n_mu device matrix per user mode; W: one tensor of
+    // workspace
+    std::vector<double*> pre, post;
+    double* W = nullptr;
+    double pipe_flops = 0;
+    // mixed precision with FP64 refinement (dense coefficients)
+    int prec = TT_FP64;
+    double tol = 1e-13;
+    int max_iter = 10;
+    std::vector<double*> Adev;   // dense A_mu (device) for the FP64 residual
+    double* R = nullptr;         // residual / correction tensor
+    double* part = nullptr;      // norm partial sums (device)
+    double* part_host = nullptr; // pinned host copy
+    double last_info[2] = {0, 0};
 
     ~tt_plan_s() {
         if (side) (void)hipStreamSynchronize(side);
@@ -93,6 +113,7 @@ struct tt_plan_s {
         if (d_tasks) (void)hipFree(d_tasks);
         if (d_items) (void)hipFree(d_items);
         if (d_status) (void)hipFree(d_status);
+        if (part_host) (void)hipHostFree(part_host);
     }
 };
 
@@ -120,26 +141,45 @@ int describe_problem(int d, const int64_t* n, int D, HostProblem& hp) {
     return TT_OK;
 }
 
-int fetch_coefficients(const double* const* T, int trans, HostProblem& hp) {
+// Place the user's coefficients (host, row-major, one vector per user mode)
+// into the internal problem.  trans != 0: the adjoint sum L x_mu T^T = G is
+// an upper quasi-triangular system in reversed index order with
+// T'[i][j] = T[n-1-j][n-1-i].
+void set_host_coefficients(HostProblem& hp, const std::vector<std::vector<double>>& Tu, int trans) {
     const int lead = hp.D - hp.d_user;
     for (int mu = 0; mu < hp.D; ++mu) {
         const int64_t nm = hp.n[mu];
         hp.T[mu].assign((size_t)(nm * nm), 0.0);
-        if (mu < lead) continue;
-        const double* src = T[mu - lead];
-        if (!src && nm > 0) return fail(TT_EINVAL, "coefficient pointer is NULL");
-        if (nm == 0) continue;
-        std::vector<double> tmp((size_t)(nm * nm));
-        TT_HIP_CHECK(hipMemcpy(tmp.data(), src, sizeof(double) * (size_t)(nm * nm), hipMemcpyDeviceToHost));
+        if (mu < lead || nm == 0) continue;
+        const std::vector<double>& src = Tu[(size_t)(mu - lead)];
         if (!trans) {
-            hp.T[mu] = std::move(tmp);
+            hp.T[mu] = src;
         } else {
-            // adjoint: sum L x_mu T^T = G becomes an upper quasi-triangular
-            // system in reversed index order with T'[i][j] = T[n-1-j][n-1-i]
             for (int64_t i = 0; i < nm; ++i)
-                for (int64_t j = 0; j < nm; ++j) hp.T[mu][i * nm + j] = tmp[(nm - 1 - j) * nm + (nm - 1 - i)];
+                for (int64_t j = 0; j < nm; ++j) hp.T[mu][i * nm + j] = src[(nm - 1 - j) * nm + (nm - 1 - i)];
         }
     }
+}
+
+// Copy d device matrices (n[mu] x n[mu]) to host vectors.
+int fetch_matrices(int d, const int64_t* n, const double* const* M, std::vector<std::vector<double>>& out) {
+    out.assign((size_t)d, {});
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t nm = n[mu];
+        out[(size_t)mu].assign((size_t)(nm * nm), 0.0);
+        if (nm == 0) continue;
+        if (!M[mu]) return fail(TT_EINVAL, "coefficient pointer is NULL");
+        TT_HIP_CHECK(hipMemcpy(out[(size_t)mu].data(), M[mu], sizeof(double) * (size_t)(nm * nm),
+                               hipMemcpyDeviceToHost));
+    }
+    return TT_OK;
+}
+
+int fetch_coefficients(const double* const* T, int trans, HostProblem& hp) {
+    std::vector<std::vector<double>> Tu;
+    int rc = fetch_matrices(hp.d_user, hp.n + (hp.D - hp.d_user), T, Tu);
+    if (rc) return rc;
+    set_host_coefficients(hp, Tu, trans);
     return TT_OK;
 }
 
@@ -149,6 +189,23 @@ int upload(const std::vector<V>& v, V** dst) {
     if (v.empty()) return TT_OK;
     if (hipMalloc((void**)dst, sizeof(V) * v.size()) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
     TT_HIP_CHECK(hipMemcpy(*dst, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice));
+    return TT_OK;
+}
+
+int upload_matrix(tt_plan_s* P, const std::vector<double>& m, double** out) {
+    *out = nullptr;
+    if (hipMalloc((void**)out, sizeof(double) * std::max<size_t>(1, m.size())) != hipSuccess)
+        return fail(TT_ENOMEM, "hipMalloc failed");
+    P->owned.push_back(*out);
+    if (!m.empty()) TT_HIP_CHECK(hipMemcpy(*out, m.data(), sizeof(double) * m.size(), hipMemcpyHostToDevice));
+    return TT_OK;
+}
+
+int alloc_tensor(tt_plan_s* P, int64_t N, double** out) {
+    *out = nullptr;
+    if (hipMalloc((void**)out, sizeof(double) * (size_t)std::max<int64_t>(1, N)) != hipSuccess)
+        return fail(TT_ENOMEM, "hipMalloc failed (workspace tensor)");
+    P->owned.push_back(*out);
     return TT_OK;
 }
 
@@ -227,9 +284,8 @@ struct ProfEvents {
     std::vector<hipEvent_t> lb, la, ub, ua;
 };
 
-int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr) {
+int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int lp = 0) {
     Schedule& s = P->sched;
-    TT_HIP_CHECK(launch_zero_int(P->d_status, 4, st));
     TT_HIP_CHECK(hipEventRecord(P->ev_start, st));
     TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->ev_start, 0));
     const size_t W = s.waves.size();
@@ -243,7 +299,7 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr) {
         TT_HIP_CHECK(hipEventRecord(P->evL[k], st));
         if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ub[k], P->side));
-        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs,
+        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp,
                                    P->side));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ua[k], P->side));
         TT_HIP_CHECK(hipEventRecord(P->evU[k], P->side));
@@ -290,6 +346,160 @@ int internal_order(const int* d, int count) {
     return D;
 }
 
+// Mode-mu view [L][n_mu][R] of the (single) problem's user tensor.
+void mode_view(const HostProblem& hp, int mu, int64_t& L, int64_t& nm, int64_t& R) {
+    const int lead = hp.D - hp.d_user;
+    L = 1;
+    R = 1;
+    for (int nu = 0; nu < hp.d_user; ++nu) {
+        if (nu < mu) L *= hp.n[lead + nu];
+        if (nu > mu) R *= hp.n[lead + nu];
+    }
+    nm = hp.n[lead + mu];
+}
+
+// Apply one mode product per user mode, in mode order, starting from src and
+// ending in fin; intermediate results alternate between fin and other.  If the
+// first target would be src itself, src is first copied to the free buffer.
+int apply_chain(tt_plan_s* P, const double* src, double* fin, double* other, const std::vector<double*>& mats,
+                int lp, hipStream_t st) {
+    const HostProblem& hp = P->sched.probs[0];
+    const int m = (int)mats.size();
+    if (m == 0) {
+        if (src != fin) TT_HIP_CHECK(launch_copy(src, fin, hp.N, st));
+        return TT_OK;
+    }
+    const double* cur = src;
+    double* t0 = ((m - 1) % 2 == 0) ? fin : other;
+    if (t0 == cur) {
+        double* o = (cur == fin) ? other : fin;
+        TT_HIP_CHECK(launch_copy(cur, o, hp.N, st));
+        cur = o;
+    }
+    for (int i = 0; i < m; ++i) {
+        double* tgt = ((m - 1 - i) % 2 == 0) ? fin : other;
+        int64_t L, nm, R;
+        mode_view(hp, i, L, nm, R);
+        TT_HIP_CHECK(launch_modeprod(cur, tgt, nullptr, mats[(size_t)i], L, (int)nm, (int)nm, R, 1.0, 0.0, lp, st));
+        cur = tgt;
+    }
+    return TT_OK;
+}
+
+// One pass of the plan's method for a single problem: B -> X.
+//   TRI:     copy, triangular solve (adjoint plans reverse the order);
+//   PAIR:    X = B x_mu C_mu^{-1} (all modes), triangular solve in X;
+//   GENERAL: B~ = B x_mu U_mu^T, triangular solve, X = X~ x_mu U_mu.
+// lp = 1 runs the recursion updates and the transforms in FP32 MFMA.
+int run_pipeline(tt_plan_s* P, const double* B, double* X, int lp, hipStream_t st) {
+    if (P->kind == KIND_TRI) {
+        int rc = prepare_inputs(P, &B, &X, st);
+        if (!rc) rc = run_schedule(P, st, nullptr, lp);
+        if (!rc) rc = finish_outputs(P, &X, st);
+        return rc;
+    }
+    const HostProblem& hp = P->sched.probs[0];
+    if (hp.N == 0) return TT_OK;
+    if (!B || !X) return fail(TT_EINVAL, "tensor pointer is NULL");
+    double* S = X;
+    int rc;
+    if (P->kind == KIND_PAIR) {
+        rc = apply_chain(P, B, X, P->W, P->pre, lp, st);
+    } else {
+        S = (hp.d_user % 2 == 0) ? X : P->W;
+        rc = apply_chain(P, B, S, (S == X) ? P->W : X, P->pre, lp, st);
+    }
+    if (rc) return rc;
+    if ((rc = set_pointers(P, &S, 1, st))) return rc;
+    if ((rc = run_schedule(P, st, nullptr, lp))) return rc;
+    if (P->kind == KIND_GENERAL) rc = apply_chain(P, S, X, P->W, P->post, lp, st);
+    return rc;
+}
+
+// Mixed precision with FP64 iterative refinement:
+//   X_0 = solve_lp(B);  repeat  R = B - sum_mu X x_mu A_mu  (FP64),
+//   D = solve_lp(R),  X += D  until ||D||_F / ||X||_F <= tol or max_iter.
+int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
+    const HostProblem& hp = P->sched.probs[0];
+    P->last_info[0] = 0;
+    P->last_info[1] = 0;
+    if (hp.N == 0) return TT_OK;
+    if (B == X) return fail(TT_EINVAL, "mixed precision needs X distinct from B (B enters every residual)");
+    int rc = run_pipeline(P, B, X, 1, st);
+    if (rc) return rc;
+    const int nb = sumsq_blocks();
+    for (int it = 1; it <= P->max_iter; ++it) {
+        TT_HIP_CHECK(launch_copy(B, P->R, hp.N, st));
+        for (int mu = 0; mu < hp.d_user; ++mu) {
+            int64_t L, nm, Rr;
+            mode_view(hp, mu, L, nm, Rr);
+            TT_HIP_CHECK(launch_modeprod(X, P->R, P->R, P->Adev[(size_t)mu], L, (int)nm, (int)nm, Rr, -1.0, 1.0, 0,
+                                         st));
+        }
+        if ((rc = run_pipeline(P, P->R, P->R, 1, st))) return rc;
+        TT_HIP_CHECK(launch_axpy(X, P->R, 1.0, hp.N, st));
+        TT_HIP_CHECK(launch_sumsq2(P->R, X, hp.N, P->part, st));
+        TT_HIP_CHECK(hipMemcpyAsync(P->part_host, P->part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+        TT_HIP_CHECK(hipStreamSynchronize(st));
+        double dd = 0, xx = 0;
+        for (int b = 0; b < nb; ++b) {
+            dd += P->part_host[2 * b];
+            xx += P->part_host[2 * b + 1];
+        }
+        const double ratio = (xx > 0) ? std::sqrt(dd / xx) : 0.0;
+        P->last_info[0] = it;
+        P->last_info[1] = ratio;
+        if (!std::isfinite(ratio)) return fail(TT_ESINGULAR, "refinement produced a non-finite correction");
+        if (ratio <= P->tol) return TT_OK;
+    }
+    return fail(TT_ENOTCONV, "mixed-precision refinement did not reach the tolerance");
+}
+
+int setup_refinement(tt_plan_s* P, const std::vector<std::vector<double>>& A, const tt_opts* opts) {
+    P->prec = opts ? opts->prec : TT_FP64;
+    if (P->prec == TT_FP64) return TT_OK;
+    if (P->prec == TT_MP_BF16) return fail(TT_EINVAL, "BF16 mixed precision is not available (use TT_MP_FP32)");
+    if (P->prec != TT_MP_FP32) return fail(TT_EINVAL, "unknown precision");
+    if (P->count != 1 || P->trans) return fail(TT_EINVAL, "mixed precision needs a single, non-adjoint problem");
+    P->tol = opts->tol > 0 ? opts->tol : 1e-13;
+    P->max_iter = opts->max_iter > 0 ? opts->max_iter : 10;
+    const HostProblem& hp = P->sched.probs[0];
+    P->Adev.assign(A.size(), nullptr);
+    int rc;
+    for (size_t mu = 0; mu < A.size(); ++mu)
+        if ((rc = upload_matrix(P, A[mu], &P->Adev[mu]))) return rc;
+    if ((rc = alloc_tensor(P, hp.N, &P->R))) return rc;
+    if (hipMalloc((void**)&P->part, sizeof(double) * 2 * sumsq_blocks()) != hipSuccess)
+        return fail(TT_ENOMEM, "hipMalloc failed");
+    P->owned.push_back(P->part);
+    if (hipHostMalloc((void**)&P->part_host, sizeof(double) * 2 * sumsq_blocks(), 0) != hipSuccess)
+        return fail(TT_ENOMEM, "hipHostMalloc failed");
+    return TT_OK;
+}
+
+// Top level of one (possibly refined) solve of a single-problem plan.
+int solve_single(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
+    TT_HIP_CHECK(launch_zero_int(P->d_status, 4, st));
+    P->last_stream = st;
+    if (P->prec != TT_FP64) return run_refined(P, B, X, st);
+    return run_pipeline(P, B, X, 0, st);
+}
+
+// Plan of a single problem from host coefficients (row-major, one vector per
+// user mode), without the device work of finish_plan.
+int plan_begin(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::vector<double>>& Tu, int trans) {
+    P->trans = trans;
+    P->count = 1;
+    P->sched.D = (d == 4) ? 4 : 3;
+    P->sched.probs.resize(1);
+    int rc = describe_problem(d, n, P->sched.D, P->sched.probs[0]);
+    if (rc) return rc;
+    set_host_coefficients(P->sched.probs[0], Tu, trans);
+    P->d_user.push_back(d);
+    (void)hipGetDevice(&P->device);
+    return TT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -324,6 +534,8 @@ int tt_plan_create_batched(tt_plan* out, int count, const int* d, const int64_t*
     if (!out) return fail(TT_EINVAL, "out is NULL");
     *out = nullptr;
     if (count < 1 || !d || !n || !T) return fail(TT_EINVAL, "bad batch arguments");
+    if (opts && opts->prec != TT_FP64)
+        return fail(TT_EINVAL, "batched plans are FP64 only (mixed precision: tt_plan_create, tt_plan_create_general)");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
     P->trans = trans ? 1 : 0;
@@ -349,15 +561,165 @@ int tt_plan_create_batched(tt_plan* out, int count, const int* d, const int64_t*
     return TT_OK;
 }
 
+// Pair form: sum_mu X x_1 C_1 .. x_mu A_mu .. x_d C_d = B.  Since
+// X x_mu A_mu = (X x_mu C_mu^{-1} A_mu) x_mu C_mu and mode products in
+// different modes commute, the operator equals the Laplace-like operator of
+// T'_mu = C_mu^{-1} A_mu followed by x_1 C_1 ... x_d C_d.  So
+// X = L(T')^{-1} (B x_1 C_1^{-1} ... x_d C_d^{-1}).  T'_mu keeps the
+// quasi-triangular pattern of A_mu exactly (row i of C^{-1} starts at column i).
+static int pair_reduce(int d, const int64_t* n, std::vector<std::vector<double>>& A,
+                       const std::vector<std::vector<double>>& C, std::vector<std::vector<double>>& Cinv) {
+    Cinv.assign((size_t)d, {});
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t m = n[mu];
+        const std::vector<double>& c = C[(size_t)mu];
+        for (int64_t i = 0; i < m; ++i) {
+            if (c[(size_t)(i * m + i)] == 0.0 || !std::isfinite(c[(size_t)(i * m + i)]))
+                return fail(TT_EINVAL, "C has a zero or non-finite diagonal entry");
+            for (int64_t j = 0; j < i; ++j)
+                if (c[(size_t)(i * m + j)] != 0.0) return fail(TT_EINVAL, "C is not upper triangular");
+        }
+        // C^{-1} column by column (back-substitution)
+        std::vector<double> ci((size_t)(m * m), 0.0);
+        for (int64_t j = 0; j < m; ++j) {
+            for (int64_t i = j; i >= 0; --i) {
+                double acc = (i == j) ? 1.0 : 0.0;
+                for (int64_t k = i + 1; k <= j; ++k) acc -= c[(size_t)(i * m + k)] * ci[(size_t)(k * m + j)];
+                ci[(size_t)(i * m + j)] = acc / c[(size_t)(i * m + i)];
+            }
+        }
+        // T' = C^{-1} A (rows of C^{-1} start at the diagonal)
+        std::vector<double> t((size_t)(m * m), 0.0);
+        const std::vector<double>& a = A[(size_t)mu];
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t k = i; k < m; ++k) {
+                const double f = ci[(size_t)(i * m + k)];
+                if (f == 0.0) continue;
+                const int64_t j0 = (k >= 1) ? k - 1 : 0;
+                for (int64_t j = j0; j < m; ++j) t[(size_t)(i * m + j)] += f * a[(size_t)(k * m + j)];
+            }
+        A[(size_t)mu] = std::move(t);
+        Cinv[(size_t)mu] = std::move(ci);
+    }
+    return TT_OK;
+}
+
+static double pipeline_flops(const HostProblem& hp, int products) {
+    double f = 0;
+    const int lead = hp.D - hp.d_user;
+    for (int mu = 0; mu < hp.d_user; ++mu) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
+    return f * products;
+}
+
 int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T,
                    const double* const* C, int trans, const tt_opts* opts) {
-    if (C) return fail(TT_EINVAL, "pair form (C != NULL) is not supported by plans");
-    return tt_plan_create_batched(out, 1, &d, &n, &T, trans, opts);
+    if (!C) {
+        if (!out) return fail(TT_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!T) return fail(TT_EINVAL, "coefficient array is NULL");
+        tt_plan p = nullptr;
+        tt_opts o64;
+        tt_opts_default(&o64);
+        if (opts) o64 = *opts;
+        o64.prec = TT_FP64;
+        int rc = tt_plan_create_batched(&p, 1, &d, &n, &T, trans, &o64);
+        if (rc) return rc;
+        std::unique_ptr<tt_plan_s> P(p);
+        if (opts && opts->prec != TT_FP64) {
+            std::vector<std::vector<double>> Tu;
+            if ((rc = fetch_matrices(d, n, T, Tu))) return rc;
+            if ((rc = setup_refinement(P.get(), Tu, opts))) return rc;
+        }
+        *out = P.release();
+        return TT_OK;
+    }
+    if (!out) return fail(TT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (trans) return fail(TT_EINVAL, "adjoint plans of the pair form are not supported");
+    if (!T) return fail(TT_EINVAL, "coefficient array is NULL");
+    if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "mixed precision is not supported for the pair form");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    HostProblem probe;
+    int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
+    if (rc) return rc;
+    std::vector<std::vector<double>> A, Cm, Cinv;
+    if ((rc = fetch_matrices(d, n, T, A))) return rc;
+    if ((rc = fetch_matrices(d, n, C, Cm))) return rc;
+    if ((rc = pair_reduce(d, n, A, Cm, Cinv))) return rc;
+    if ((rc = plan_begin(P.get(), d, n, A, 0))) return rc;
+    P->kind = KIND_PAIR;
+    if ((rc = finish_plan(P.get(), opts ? opts->nmin : 0))) return rc;
+    const HostProblem& hp = P->sched.probs[0];
+    P->pre.assign((size_t)d, nullptr);
+    for (int mu = 0; mu < d; ++mu)
+        if ((rc = upload_matrix(P.get(), Cinv[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
+    if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
+    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 1);
+    P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P.release();
+    return TT_OK;
+}
+
+int tt_plan_create_general(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
+                           const tt_opts* opts) {
+    if (!out) return fail(TT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A_host) return fail(TT_EINVAL, "coefficient array is NULL");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    HostProblem probe;
+    int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
+    if (rc) return rc;
+    std::vector<std::vector<double>> A((size_t)d), T((size_t)d), U((size_t)d), Ut((size_t)d);
+    std::vector<int> ni((size_t)d);
+    std::vector<const double*> ap((size_t)d);
+    std::vector<double*> tp((size_t)d), up((size_t)d);
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] > 16384) return fail(TT_EINVAL, "mode size too large for the host Schur decomposition");
+        if (!A_host[mu] && n[mu] > 0) return fail(TT_EINVAL, "coefficient pointer is NULL");
+        const size_t nn = (size_t)(n[mu] * n[mu]);
+        A[(size_t)mu].assign(A_host[mu], A_host[mu] + nn);
+        T[(size_t)mu].assign(nn, 0.0);
+        U[(size_t)mu].assign(nn, 0.0);
+        ni[(size_t)mu] = (int)n[mu];
+        ap[(size_t)mu] = A[(size_t)mu].data();
+        tp[(size_t)mu] = T[(size_t)mu].data();
+        up[(size_t)mu] = U[(size_t)mu].data();
+    }
+    std::string err;
+    if ((rc = schur_real_many(d, ni.data(), ap.data(), tp.data(), up.data(), err))) return fail(rc, err);
+    P->schur_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int mu = 0; mu < d; ++mu) {
+        const int64_t m = n[mu];
+        Ut[(size_t)mu].assign((size_t)(m * m), 0.0);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < m; ++j) Ut[(size_t)mu][(size_t)(i * m + j)] = U[(size_t)mu][(size_t)(j * m + i)];
+    }
+    if ((rc = plan_begin(P.get(), d, n, T, 0))) return rc;
+    P->kind = KIND_GENERAL;
+    if ((rc = finish_plan(P.get(), opts ? opts->nmin : 0))) return rc;
+    const HostProblem& hp = P->sched.probs[0];
+    P->pre.assign((size_t)d, nullptr);
+    P->post.assign((size_t)d, nullptr);
+    for (int mu = 0; mu < d; ++mu) {
+        if ((rc = upload_matrix(P.get(), Ut[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
+        if ((rc = upload_matrix(P.get(), U[(size_t)mu], &P->post[(size_t)mu]))) return rc;
+    }
+    if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
+    if ((rc = setup_refinement(P.get(), A, opts))) return rc;
+    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 2);
+    P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P.release();
+    return TT_OK;
 }
 
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X, void* stream) {
     if (!plan || !B || !X) return fail(TT_EINVAL, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
+    if (plan->count == 1) return solve_single(plan, B[0], X[0], st);
+    TT_HIP_CHECK(launch_zero_int(plan->d_status, 4, st));
+    plan->last_stream = st;
     int rc = prepare_inputs(plan, B, X, st);
     if (rc) return rc;
     rc = run_schedule(plan, st);
@@ -368,13 +730,25 @@ int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X
 int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream) {
     if (!plan) return fail(TT_EINVAL, "plan is NULL");
     if (plan->count != 1) return fail(TT_EINVAL, "batched plan: use tt_plan_solve_batched");
-    return tt_plan_solve_batched(plan, &B, &X, stream);
+    return solve_single(plan, B, X, (hipStream_t)stream);
+}
+
+int tt_plan_info(tt_plan plan, double* out) {
+    if (!plan || !out) return fail(TT_EINVAL, "NULL argument");
+    out[0] = plan->last_info[0];
+    out[1] = plan->last_info[1];
+    out[2] = plan->build_seconds;
+    out[3] = plan->schur_seconds;
+    return TT_OK;
 }
 
 int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, double* out) {
     if (!plan || !out) return fail(TT_EINVAL, "NULL argument");
-    if (plan->count != 1) return fail(TT_EINVAL, "profile needs a single-problem plan");
+    if (plan->count != 1 || plan->kind != KIND_TRI || plan->prec != TT_FP64)
+        return fail(TT_EINVAL, "profile needs a single-problem FP64 triangular plan");
     hipStream_t st = (hipStream_t)stream;
+    TT_HIP_CHECK(launch_zero_int(plan->d_status, 4, st));
+    plan->last_stream = st;
     const size_t W = plan->sched.waves.size();
     ProfEvents pe;
     for (auto* v : {&pe.lb, &pe.la, &pe.ub, &pe.ua}) {
@@ -425,23 +799,32 @@ int tt_plan_status(tt_plan plan) {
     return TT_OK;
 }
 
-double tt_plan_flops(tt_plan plan) { return plan ? plan->sched.stats.flops : 0.0; }
+double tt_plan_flops(tt_plan plan) {
+    if (!plan) return 0.0;
+    return plan->kind == KIND_TRI ? plan->sched.stats.flops : plan->pipe_flops;
+}
 
 int tt_plan_destroy(tt_plan plan) {
     delete plan;
     return TT_OK;
 }
 
+static void report(tt_plan_s* P, tt_opts* opts) {
+    if (!opts) return;
+    opts->info[0] = P->last_info[0];
+    opts->info[1] = P->last_info[1];
+    opts->info[2] = P->build_seconds;
+}
+
 int solve_tri_tensor(int d, const int64_t* n, const double* const* T, const double* const* C,
                      const double* B, double* X, tt_opts* opts) {
-    if (C) return fail(TT_EINVAL, "pair form is not available in this build");
     tt_plan p = nullptr;
-    int rc = tt_plan_create(&p, d, n, T, nullptr, 0, opts);
+    int rc = tt_plan_create(&p, d, n, T, C, 0, opts);
     if (rc) return rc;
     std::unique_ptr<tt_plan_s> guard(p);
     hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
-    if (opts) opts->info[2] = p->build_seconds;
     rc = tt_plan_solve(p, B, X, st);
+    report(p, opts);
     if (rc) return rc;
     return tt_plan_status(p);
 }
@@ -461,23 +844,95 @@ int solve_tri_tensor_batched(int count, const int* d, const int64_t* const* n,
 
 int solve_general_tensor(int d, const int64_t* n, const double* const* A_host, const double* B,
                          double* X, tt_opts* opts) {
-    (void)d; (void)n; (void)A_host; (void)B; (void)X; (void)opts;
-    return fail(TT_EINVAL, "solve_general_tensor is not available in this build");
+    tt_plan p = nullptr;
+    int rc = tt_plan_create_general(&p, d, n, A_host, opts);
+    if (rc) return rc;
+    std::unique_ptr<tt_plan_s> guard(p);
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    rc = tt_plan_solve(p, B, X, st);
+    report(p, opts);
+    if (rc) return rc;
+    return tt_plan_status(p);
 }
 
-int solve_backward(int d, const int64_t* n, const double* const* T, const double* X,
-                   const double* G, double* dB, double* const* dT, int dense_grad, tt_opts* opts) {
-    (void)d; (void)n; (void)T; (void)X; (void)G; (void)dB; (void)dT; (void)dense_grad; (void)opts;
-    return fail(TT_EINVAL, "solve_backward is not available in this build");
+// Coefficient gradients of one problem: dT[mu] = -Lam_(mu) X_(mu)^T, masked
+// to the pattern of T[mu] unless dense.  W: split-K workspace.
+static int coefficient_grads(int d, const int64_t* n, const double* const* T, const double* Lam, const double* X,
+                             double* const* dT, int dense, double* W, hipStream_t st) {
+    int64_t N = 1;
+    for (int mu = 0; mu < d; ++mu) N *= n[mu];
+    for (int mu = 0; mu < d; ++mu) {
+        if (!dT[mu] || n[mu] == 0) continue;
+        int64_t L = 1, R = 1;
+        for (int nu = 0; nu < d; ++nu) {
+            if (nu < mu) L *= n[nu];
+            if (nu > mu) R *= n[nu];
+        }
+        const int ns = gram_splits((int)n[mu], L * R);
+        TT_HIP_CHECK(launch_gram(Lam, X, W, ns, (int)n[mu], L, R, st));
+        TT_HIP_CHECK(launch_gram_reduce(W, ns, (int)n[mu], T[mu], dense, -1.0, dT[mu], st));
+    }
+    return TT_OK;
+}
+
+static size_t grad_workspace(int d, const int64_t* n) {
+    int64_t N = 1;
+    for (int mu = 0; mu < d; ++mu) N *= n[mu];
+    size_t w = 1;
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] == 0) continue;
+        const size_t ns = (size_t)gram_splits((int)n[mu], N / n[mu]);
+        w = std::max(w, ns * (size_t)(n[mu] * n[mu]));
+    }
+    return w;
 }
 
 int solve_backward_batched(int count, const int* d, const int64_t* const* n,
                            const double* const* const* T, const double* const* X,
                            const double* const* G, double* const* dB, double* const* const* dT,
                            int dense_grad, tt_opts* opts) {
-    (void)count; (void)d; (void)n; (void)T; (void)X; (void)G; (void)dB; (void)dT; (void)dense_grad;
-    (void)opts;
-    return fail(TT_EINVAL, "solve_backward_batched is not available in this build");
+    if (count < 1 || !d || !n || !T || !G || !dB) return fail(TT_EINVAL, "NULL argument");
+    if (dT && !X) return fail(TT_EINVAL, "X is needed for the coefficient gradients");
+    tt_plan p = nullptr;
+    int rc = tt_plan_create_batched(&p, count, d, n, T, 1, opts);
+    if (rc) return rc;
+    std::unique_ptr<tt_plan_s> guard(p);
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    // Lam: sum_mu Lam x_mu T_mu^T = G, into dB
+    if ((rc = tt_plan_solve_batched(p, G, dB, st))) return rc;
+    if (dT) {
+        size_t wmax = 1;
+        for (int i = 0; i < count; ++i)
+            if (dT[i]) wmax = std::max(wmax, grad_workspace(d[i], n[i]));
+        double* W = nullptr;
+        if (hipMalloc((void**)&W, sizeof(double) * wmax) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
+        p->owned.push_back(W);
+        for (int i = 0; i < count; ++i) {
+            if (!dT[i]) continue;
+            if (!X[i] && p->sched.probs[(size_t)i].N > 0) return fail(TT_EINVAL, "X pointer is NULL");
+            if ((rc = coefficient_grads(d[i], n[i], T[i], dB[i], X[i], dT[i], dense_grad, W, st))) return rc;
+        }
+    }
+    return tt_plan_status(p);
+}
+
+int solve_backward(int d, const int64_t* n, const double* const* T, const double* X,
+                   const double* G, double* dB, double* const* dT, int dense_grad, tt_opts* opts) {
+    const double* const* Tb[1] = {T};
+    const double* Xb[1] = {X};
+    const double* Gb[1] = {G};
+    double* dBb[1] = {dB};
+    double* const* dTb[1] = {dT};
+    return solve_backward_batched(1, &d, &n, Tb, Xb, Gb, dBb, dT ? dTb : nullptr, dense_grad, opts);
+}
+
+// Host-only real Schur decomposition (the host step of solve_general_tensor).
+int tt_schur_host(int n, const double* A, double* T, double* U) {
+    if (n < 0 || (n > 0 && (!A || !T || !U))) return fail(TT_EINVAL, "bad arguments");
+    std::string err;
+    int rc = schur_real(n, A, T, U, err);
+    if (rc) return fail(rc, err);
+    return TT_OK;
 }
 
 // Host-only schedule query (no GPU calls): builds the plan of a problem with

@@ -1,0 +1,462 @@
+// Dense tensor kernels around the triangular solve (gfx950, FP64 MFMA):
+//   modeprod_kernel - Y = alpha (X x_mu M) + beta Z, the mode-mu product of
+//                     Sec. 2 used by the Schur transforms of Algorithm 1
+//                     (B x_mu U_mu^T before the solve, X x_mu U_mu after),
+//                     by the C_mu^{-1} reduction of the pair form and by the
+//                     FP64 residual of iterative refinement;
+//   gram_kernel     - split-K partial sums of P_(mu) Q_(mu)^T, the
+//                     coefficient gradient -Lam_(mu) X_(mu)^T of the adjoint;
+//   gram_reduce_kernel, axpy, norms and precision conversions.
+//
+// A tensor of shape (n_1..n_d) in C order is viewed, for mode mu, as
+// [L][n_mu][R] with L = prod_{nu<mu} n_nu and R = prod_{nu>mu} n_nu.
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+constexpr int kDT = 64;      // output tile edge
+constexpr int kDKC = 16;     // K chunk staged through LDS
+constexpr int kDRow = 80;    // LDS row pitch (doubles)
+constexpr int kDThreads = 256;
+
+// 2x2 blocks of 16x16x4 MFMA per wave over one K chunk.  LP = false:
+// v_mfma_f64_16x16x4f64; LP = true: operands rounded to FP32 and
+// v_mfma_f32_16x16x4f32 with FP32 accumulation.  Lane layout: A[i][k] from
+// lane 16k + i, B[k][j] from lane 16k + j; result element v of lane 16 g + j
+// is D[4 v + g][j] (FP64) or D[4 g + v][j] (FP32).
+template <bool LP>
+struct MAcc {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct MAcc<true> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+template <bool LP>
+__device__ inline int mrow(int v, int g) {
+    return LP ? 4 * g + v : 4 * v + g;
+}
+
+template <bool LP>
+__device__ inline void mfma_chunk16(const double* As, const double* Bs, int wr, int wc, int li, int lk,
+                                    typename MAcc<LP>::type (&acc)[2][2]) {
+#pragma unroll
+    for (int kk = 0; kk < kDKC; kk += 4) {
+        const double* Ak = As + (kk + lk) * kDRow;
+        const double* Bk = Bs + (kk + lk) * kDRow;
+        double a0 = Ak[wr + li], a1 = Ak[wr + 16 + li];
+        double b0 = Bk[wc + li], b1 = Bk[wc + 16 + li];
+        if constexpr (LP) {
+            const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb1, acc[1][1], 0, 0, 0);
+        } else {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Renumber so that every XCD works on a contiguous range of logical tiles:
+// tiles that share an operand then share an L2.
+__device__ inline int64_t xcd_tile(int64_t b, int64_t nblocks) {
+    if (nblocks % 8 != 0) return b;
+    return (b % 8) * (nblocks / 8) + b / 8;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Mode product.  Y[l, i, r] = alpha * sum_j M[i, j] X[l, j, r] + beta * Z[l, i, r]
+// with M row-major nout x nin (ld = nin).  Z may equal Y (read before write);
+// Y must not overlap X.
+//   R > 1 : MFMA rows = i (M rows), columns = c = l R + r (X columns).
+//   R == 1: MFMA rows = l (X rows, contiguous along j), columns = i.
+// Grid: row tiles x column tiles, flattened, renumbered per XCD.
+// ---------------------------------------------------------------------------
+template <bool LP>
+__global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __restrict__ X, double* Y,
+                                                             const double* Z,
+                                                             const double* __restrict__ M, int64_t L,
+                                                             int nin, int nout, int64_t R, double alpha,
+                                                             double beta) {
+    __shared__ double As[kDKC * kDRow];
+    __shared__ double Bs[kDKC * kDRow];
+    __shared__ int64_t colOff[kDT];
+    const int tid = threadIdx.x;
+    const bool colpath = R > 1;
+    const int64_t rows = colpath ? nout : L;
+    const int64_t cols = colpath ? L * R : nout;
+    const int64_t nrt = (rows + kDT - 1) / kDT;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t row0 = (t % nrt) * kDT;
+    const int64_t col0 = (t / nrt) * kDT;
+    const int K = nin;
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    typename MAcc<LP>::type acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename MAcc<LP>::type{0, 0, 0, 0};
+    const int nchunk = (K + kDKC - 1) / kDKC;
+
+    if (colpath) {
+        if (tid < kDT) {
+            int64_t c = col0 + tid;
+            int64_t l = c / R, r = c - (c / R) * R;
+            colOff[tid] = (c < cols) ? l * (int64_t)nin * R + r : 0;
+        }
+        __syncthreads();
+        const int la_r = tid >> 2, la_k = (tid & 3) * 4;
+        const int lb_k = tid >> 4, lb_c = (tid & 15) * 4;
+        double ra[4], rb[4];
+        int64_t boff[4];
+        bool bval[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            boff[i] = colOff[lb_c + i];
+            bval[i] = (col0 + lb_c + i) < cols;
+        }
+        const bool aval = (row0 + la_r) < rows;
+        const double* Arow = M + (row0 + la_r) * (int64_t)nin;
+        auto gload = [&](int kc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int k = kc + la_k + i;
+                ra[i] = (aval && k < K) ? Arow[k] : 0.0;
+            }
+            int kb = kc + lb_k;
+            bool kv = kb < K;
+            int64_t roff = (int64_t)kb * R;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rb[i] = (kv && bval[i]) ? X[boff[i] + roff] : 0.0;
+        };
+        gload(0);
+        for (int ch = 0; ch < nchunk; ++ch) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) As[(la_k + i) * kDRow + la_r] = ra[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Bs[lb_k * kDRow + lb_c + i] = rb[i];
+            __syncthreads();
+            if (ch + 1 < nchunk) gload((ch + 1) * kDKC);
+            mfma_chunk16<LP>(As, Bs, wr, wc, li, lk, acc);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = wc + 16 * j + li;
+            if (col0 + c >= cols) continue;
+            const int64_t c64 = col0 + c;
+            const int64_t l = c64 / R, r = c64 - l * R;
+            const int64_t obase = l * (int64_t)nout * R + r;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = row0 + wr + 16 * i + mrow<LP>(v, lk);
+                    if (row < rows) {
+                        const int64_t o = obase + row * R;
+                        double val = alpha * (double)acc[i][j][v];
+                        if (beta != 0.0) val += beta * Z[o];
+                        Y[o] = val;
+                    }
+                }
+        }
+    } else {
+        // rows l (X[l][0..nin)), columns i (M[i][0..nin)), both contiguous in k
+        const int lr = tid >> 2, lk4 = (tid & 3) * 4;
+        const bool xv = (row0 + lr) < rows;
+        const bool mv = (col0 + lr) < cols;
+        const double* Xrow = X + (row0 + lr) * (int64_t)nin;
+        const double* Mrow = M + (col0 + lr) * (int64_t)nin;
+        double ra[4], rb[4];
+        auto gload = [&](int kc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                int k = kc + lk4 + i;
+                ra[i] = (xv && k < K) ? Xrow[k] : 0.0;
+                rb[i] = (mv && k < K) ? Mrow[k] : 0.0;
+            }
+        };
+        gload(0);
+        for (int ch = 0; ch < nchunk; ++ch) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                As[(lk4 + i) * kDRow + lr] = ra[i];
+                Bs[(lk4 + i) * kDRow + lr] = rb[i];
+            }
+            __syncthreads();
+            if (ch + 1 < nchunk) gload((ch + 1) * kDKC);
+            mfma_chunk16<LP>(As, Bs, wr, wc, li, lk, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t l = row0 + wr + 16 * i + mrow<LP>(v, lk);
+                if (l >= rows) continue;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int64_t col = col0 + wc + 16 * j + li;
+                    if (col < cols) {
+                        const int64_t o = l * nout + col;
+                        double val = alpha * (double)acc[i][j][v];
+                        if (beta != 0.0) val += beta * Z[o];
+                        Y[o] = val;
+                    }
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K Gram product of two tensors of the same shape [L][n][R]:
+//   W[s][a][b] = sum_{k in chunk s} P[a, k] Q[b, k],  k = l R + r,
+// P[a, k] = P[l n R + a R + r].  One workgroup per (a tile, b tile, chunk).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kDThreads) void gram_kernel(const double* __restrict__ P,
+                                                         const double* __restrict__ Q,
+                                                         double* __restrict__ W, int n, int64_t L,
+                                                         int64_t R, int64_t kchunk) {
+    __shared__ double As[kDKC * kDRow];
+    __shared__ double Bs[kDKC * kDRow];
+    __shared__ int64_t kOff[kDKC];
+    const int tid = threadIdx.x;
+    const int nt = (n + kDT - 1) / kDT;
+    const int a0 = (blockIdx.x % nt) * kDT;
+    const int b0 = (blockIdx.x / nt) * kDT;
+    const int s = blockIdx.y;
+    const int64_t K = L * R;
+    const int64_t kbeg = (int64_t)s * kchunk;
+    const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+    const int64_t nR = (int64_t)n * R;
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    MAcc<false>::type acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = MAcc<false>::type{0.0, 0.0, 0.0, 0.0};
+
+    if (R > 1) {
+        // thread: row a = tid / 4 (of both tiles), 4 consecutive k
+        const int ar = tid >> 2, ak = (tid & 3) * 4;
+        const bool pa = (a0 + ar) < n, qb = (b0 + ar) < n;
+        const double* Pr = P + (int64_t)(a0 + ar) * R;
+        const double* Qr = Q + (int64_t)(b0 + ar) * R;
+        double ra[4], rb[4];
+        for (int64_t kc = kbeg; kc < kend; kc += kDKC) {
+            __syncthreads();
+            if (tid < kDKC) {
+                int64_t k = kc + tid;
+                int64_t l = k / R;
+                kOff[tid] = (k < kend) ? l * nR + (k - l * R) : -1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t o = kOff[ak + i];
+                ra[i] = (pa && o >= 0) ? Pr[o] : 0.0;
+                rb[i] = (qb && o >= 0) ? Qr[o] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                As[(ak + i) * kDRow + ar] = ra[i];
+                Bs[(ak + i) * kDRow + ar] = rb[i];
+            }
+            __syncthreads();
+            mfma_chunk16<false>(As, Bs, wr, wc, li, lk, acc);
+        }
+    } else {
+        // R == 1: P[l][a], contiguous along a; thread: k = tid / 16, 4 consecutive a
+        const int kk = tid >> 4, ac = (tid & 15) * 4;
+        double ra[4], rb[4];
+        for (int64_t kc = kbeg; kc < kend; kc += kDKC) {
+            const int64_t k = kc + kk;
+            const bool kv = k < kend;
+            const double* Pr = P + k * n;
+            const double* Qr = Q + k * n;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ra[i] = (kv && a0 + ac + i < n) ? Pr[a0 + ac + i] : 0.0;
+                rb[i] = (kv && b0 + ac + i < n) ? Qr[b0 + ac + i] : 0.0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                As[kk * kDRow + ac + i] = ra[i];
+                Bs[kk * kDRow + ac + i] = rb[i];
+            }
+            __syncthreads();
+            mfma_chunk16<false>(As, Bs, wr, wc, li, lk, acc);
+        }
+    }
+    double* Ws = W + (int64_t)s * n * n;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = a0 + wr + 16 * i + mrow<false>(v, lk);
+            if (a >= n) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int b = b0 + wc + 16 * j + li;
+                if (b < n) Ws[(int64_t)a * n + b] = acc[i][j][v];
+            }
+        }
+}
+
+// out[a][b] = scale * sum_s W[s][a][b], masked to the quasi-triangular pattern
+// of T (a <= b, or a == b + 1 with T[a][b] != 0) unless dense != 0.
+__global__ void gram_reduce_kernel(const double* __restrict__ W, int nsplit, int n,
+                                   const double* __restrict__ T, int dense, double scale,
+                                   double* __restrict__ out) {
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / n), b = (int)(e - (e / n) * n);
+        bool keep = dense || a <= b || (a == b + 1 && T[e] != 0.0);
+        double acc = 0.0;
+        if (keep)
+            for (int s = 0; s < nsplit; ++s) acc += W[(int64_t)s * nn + e];
+        out[e] = keep ? scale * acc : 0.0;
+    }
+}
+
+__global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += a * x[i];
+}
+
+// Per-block partial sums of squares of x and of y (deterministic order).
+__global__ void sumsq2_kernel(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                              double* __restrict__ part) {
+    __shared__ double sx[256], sy[256];
+    double ax = 0.0, ay = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double a = x[i], b = y ? y[i] : 0.0;
+        ax += a * a;
+        ay += b * b;
+    }
+    sx[threadIdx.x] = ax;
+    sy[threadIdx.x] = ay;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sx[threadIdx.x] += sx[threadIdx.x + w];
+            sy[threadIdx.x] += sy[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sx[0];
+        part[2 * blockIdx.x + 1] = sy[0];
+    }
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+
+__global__ void f32_to_f64_kernel(const float* __restrict__ x, double* __restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static unsigned elem_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (unsigned)b;
+}
+
+hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
+                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st) {
+    if (L <= 0 || R <= 0 || nout <= 0) return hipSuccess;
+    const int64_t rows = (R > 1) ? nout : L;
+    const int64_t cols = (R > 1) ? L * R : nout;
+    const int64_t tiles = ((rows + kDT - 1) / kDT) * ((cols + kDT - 1) / kDT);
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    if (lp)
+        hipLaunchKernelGGL(modeprod_kernel<true>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+                           nout, R, alpha, beta);
+    else
+        hipLaunchKernelGGL(modeprod_kernel<false>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+                           nout, R, alpha, beta);
+    return hipGetLastError();
+}
+
+int gram_splits(int n, int64_t K) {
+    const int nt = (n + kDT - 1) / kDT;
+    int64_t want = 2048 / (nt * nt);
+    int64_t maxs = K / 512;
+    if (want > maxs) want = maxs;
+    if (want < 1) want = 1;
+    if (want > 1024) want = 1024;
+    return (int)want;
+}
+
+hipError_t launch_gram(const double* P, const double* Q, double* W, int nsplit, int n, int64_t L, int64_t R,
+                       hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int nt = (n + kDT - 1) / kDT;
+    const int64_t K = L * R;
+    int64_t kchunk = (K + nsplit - 1) / nsplit;
+    kchunk = (kchunk + kDKC - 1) / kDKC * kDKC;
+    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(nt * nt), (unsigned)nsplit), dim3(kDThreads), 0, st, P, Q, W,
+                       n, L, R, kchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const double* W, int nsplit, int n, const double* T, int dense, double scale,
+                              double* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gram_reduce_kernel, dim3(elem_grid((int64_t)n * n)), dim3(256), 0, st, W, nsplit, n, T,
+                       dense, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axpy_kernel, dim3(elem_grid(n)), dim3(256), 0, st, y, x, a, n);
+    return hipGetLastError();
+}
+
+int sumsq_blocks() { return 512; }
+
+hipError_t launch_sumsq2(const double* x, const double* y, int64_t n, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(sumsq2_kernel, dim3(sumsq_blocks()), dim3(256), 0, st, x, y, n, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f64_to_f32_kernel, dim3(elem_grid(n)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float* x, double* y, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f32_to_f64_kernel, dim3(elem_grid(n)), dim3(256), 0, st, x, y, n);
+    return hipGetLastError();
+}
+
+}  // namespace tt

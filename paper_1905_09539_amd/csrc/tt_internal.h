@@ -121,8 +121,30 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
                        const ProbDesc* probs, int* status, const int* bmax, int lds_bytes,
                        hipStream_t st);
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
-                         int64_t count, const ProbDesc* probs, hipStream_t st);
+                         int64_t count, const ProbDesc* probs, int lp, hipStream_t st);
 hipError_t launch_zero_int(int* p, int count, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
+
+// Dense kernels (tt_dense.hip).  Tensor viewed as [L][n_mu][R] for mode mu.
+// Y = alpha (X x_mu M) + beta Z with M row-major nout x nin; Z may be Y.
+hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
+                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st);
+// Split-K Gram product W[s] = P_(mu) Q_(mu)^T over K chunk s, then
+// out = scale * sum_s W[s] masked to the pattern of T unless dense.
+int gram_splits(int n, int64_t K);
+hipError_t launch_gram(const double* P, const double* Q, double* W, int nsplit, int n, int64_t L, int64_t R,
+                       hipStream_t st);
+hipError_t launch_gram_reduce(const double* W, int nsplit, int n, const double* T, int dense, double scale,
+                              double* out, hipStream_t st);
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+int sumsq_blocks();
+hipError_t launch_sumsq2(const double* x, const double* y, int64_t n, double* part, hipStream_t st);
+hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t st);
+hipError_t launch_f32_to_f64(const float* x, double* y, int64_t n, hipStream_t st);
+
+// Host real Schur decomposition A = U T U^T (tt_schur.cpp), row-major.
+int schur_real(int n, const double* A, double* T, double* U, std::string& err);
+int schur_real_many(int count, const int* n, const double* const* A, double* const* T, double* const* U,
+                    std::string& err);
 
 }  // namespace tt

@@ -862,21 +862,49 @@ __device__ inline int64_t pencil_col_offset(const UpdDesc& t, int c) {
     return off;
 }
 
+// LP = false: FP64 MFMA.  LP = true: operands rounded to FP32 and
+// v_mfma_f32_16x16x4f32 with FP32 accumulation (the low-precision updates of
+// mixed-precision refinement); its result element v of lane 16 g + j is
+// D[4 g + v][j] instead of the FP64 instruction's D[4 v + g][j].
+template <bool LP>
+struct MfmaAcc {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct MfmaAcc<true> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+
+template <bool LP>
+__device__ inline int mfma_row(int v, int g) {
+    return LP ? 4 * g + v : 4 * v + g;
+}
+
+template <bool LP>
 __device__ inline void mfma_chunk(const double* As, const double* Bs, int wr, int wc, int li, int lk,
-                                  dbl4 (&acc)[2][2]) {
+                                  typename MfmaAcc<LP>::type (&acc)[2][2]) {
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 4) {
         const double* Ak = As + (kk + lk) * kLdsRow;
         const double* Bk = Bs + (kk + lk) * kLdsRow;
         double a0 = Ak[wr + li], a1 = Ak[wr + 16 + li];
         double b0 = Bk[wc + li], b1 = Bk[wc + 16 + li];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        if constexpr (LP) {
+            const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb1, acc[1][1], 0, 0, 0);
+        } else {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
     }
 }
 
+template <bool LP>
 __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restrict__ tasks,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t first,
@@ -909,11 +937,11 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    dbl4 acc[2][2];
+    typename MfmaAcc<LP>::type acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
     const int nchunk = (t.K + kKC - 1) / kKC;
 
     if (!right) {
@@ -952,7 +980,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             for (int i = 0; i < 4; ++i) Bs[lb_k * kLdsRow + lb_c + i] = rb[i];
             __syncthreads();
             if (ch + 1 < nchunk) gload((ch + 1) * kKC);
-            mfma_chunk(As, Bs, wr, wc, li, lk, acc);
+            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -963,10 +991,10 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int r = wr + 16 * i + 4 * v + lk;
+                    const int r = wr + 16 * i + mfma_row<LP>(v, lk);
                     if (row0 + r < t.M) {
                         double* p = C + coff + (int64_t)(t.r0 + row0 + r) * smu;
-                        const double val = sgn * acc[i][j][v];
+                        const double val = sgn * (double)acc[i][j][v];
                         *p = store ? val : *p + val;
                     }
                 }
@@ -997,13 +1025,13 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             }
             __syncthreads();
             if (ch + 1 < nchunk) gload((ch + 1) * kKC);
-            mfma_chunk(As, Bs, wr, wc, li, lk, acc);
+            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int c = wr + 16 * i + 4 * v + lk;
+                const int c = wr + 16 * i + mfma_row<LP>(v, lk);
                 if (col0 + c >= t.P) continue;
                 const int64_t coff = colOff[c];
 #pragma unroll
@@ -1011,7 +1039,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                     const int r = wc + 16 * j + li;
                     if (row0 + r < t.M) {
                         double* p = C + coff + t.r0 + row0 + r;
-                        const double val = sgn * acc[i][j][v];
+                        const double val = sgn * (double)acc[i][j][v];
                         *p = store ? val : *p + val;
                     }
                 }
@@ -1056,9 +1084,14 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
 }
 
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
-                         int64_t count, const ProbDesc* probs, hipStream_t st) {
+                         int64_t count, const ProbDesc* probs, int lp, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(upd_kernel, dim3((unsigned)count), dim3(kUpdThreads), 0, st, tasks, items, first, probs, D);
+    if (lp)
+        hipLaunchKernelGGL(upd_kernel<true>, dim3((unsigned)count), dim3(kUpdThreads), 0, st, tasks, items, first,
+                           probs, D);
+    else
+        hipLaunchKernelGGL(upd_kernel<false>, dim3((unsigned)count), dim3(kUpdThreads), 0, st, tasks, items, first,
+                           probs, D);
     return hipGetLastError();
 }
 

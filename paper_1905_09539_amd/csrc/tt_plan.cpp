@@ -48,22 +48,20 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
                   std::to_string(i);
             return TT_EINVAL;
         }
-    // Blocks of at most b rows where possible: ideal boundaries at multiples
-    // of b, each moved to the previous row when it would cut a 2x2 block.
-    // Algorithm 2 moves k to k + 1 instead; any split with A(k+1, k) = 0 is
-    // valid (Sec. 2.1) and the earlier one keeps blocks within b rows.  A
-    // short last block (under b/2 rows) is merged into its neighbour.
+    // m = ceil(n / b) blocks of near-equal size (at most b rows), each ideal
+    // boundary moved to the previous row when it would cut a 2x2 block, so
+    // blocks have at most b + 1 rows.  Algorithm 2 moves k to k + 1 instead;
+    // any split with A(k+1, k) = 0 is valid (Sec. 2.1).
     auto cuts_bump = [&](int64_t k) { return k > 0 && k < n && T[k * n + k - 1] != 0.0; };
+    const int64_t m = (n + b - 1) / b;
     bst.push_back(0);
-    for (int64_t pos = b; pos < n; pos += b) {
-        int64_t q = pos;
+    for (int64_t k = 1; k < m; ++k) {
+        int64_t q = (k * n + m / 2) / m;
         if (cuts_bump(q)) --q;
         if (q <= bst.back()) continue;
         bst.push_back((int32_t)q);
     }
     bst.push_back((int32_t)n);
-    if (bst.size() >= 3 && bst[bst.size() - 1] - bst[bst.size() - 2] < std::max(1, b / 2))
-        bst.erase(bst.end() - 2);
     for (size_t i = 0; i + 1 < bst.size(); ++i)
         if (bst[i + 1] - bst[i] > 32) {
             err = "leaf block larger than 32 rows; use nmin <= 20";

@@ -1,0 +1,248 @@
+// Host real Schur decomposition A = U T U^T, the reduction step of
+// Algorithm 1 (Sec. 2): T upper quasi-triangular with 1x1 and 2x2 diagonal
+// blocks, U orthogonal.  Method (Golub & Van Loan, Matrix Computations,
+// Sec. 7.4-7.5): Householder reduction to upper Hessenberg form, then the
+// Francis implicit double-shift QR iteration with deflation on the full
+// matrix (so that T and U are both kept), and finally every 2x2 block
+// standardised by a plane rotation: real eigenvalues -> split into two 1x1
+// blocks; complex pair -> equal diagonal entries and off-diagonals of
+// opposite sign.  Row-major n x n storage throughout.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+struct Mat {
+    int n;
+    std::vector<double> a;
+    explicit Mat(int n_) : n(n_), a((size_t)n_ * n_, 0.0) {}
+    double& operator()(int i, int j) { return a[(size_t)i * n + j]; }
+    double operator()(int i, int j) const { return a[(size_t)i * n + j]; }
+};
+
+// Householder vector v (v[0] = 1) and beta with (I - beta v v^T) x = alpha e_1.
+// Returns beta (0 when x is already a multiple of e_1).
+double householder(const double* x, int m, double* v) {
+    double sigma = 0.0;
+    for (int i = 1; i < m; ++i) sigma += x[i] * x[i];
+    v[0] = 1.0;
+    for (int i = 1; i < m; ++i) v[i] = x[i];
+    if (sigma == 0.0) return 0.0;
+    const double mu = std::sqrt(x[0] * x[0] + sigma);
+    // v0 = x0 - mu computed without cancellation
+    const double v0 = (x[0] <= 0.0) ? x[0] - mu : -sigma / (x[0] + mu);
+    const double beta = 2.0 * v0 * v0 / (sigma + v0 * v0);
+    for (int i = 1; i < m; ++i) v[i] = x[i] / v0;
+    return beta;
+}
+
+// rows r0..r0+m-1 of H, columns c0..c1-1:  H <- (I - beta v v^T) H
+void apply_left(Mat& H, int r0, int m, int c0, int c1, const double* v, double beta) {
+    if (beta == 0.0) return;
+    for (int j = c0; j < c1; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += v[i] * H(r0 + i, j);
+        s *= beta;
+        for (int i = 0; i < m; ++i) H(r0 + i, j) -= s * v[i];
+    }
+}
+
+// columns c0..c0+m-1 of H, rows r0..r1-1:  H <- H (I - beta v v^T)
+void apply_right(Mat& H, int c0, int m, int r0, int r1, const double* v, double beta) {
+    if (beta == 0.0) return;
+    for (int i = r0; i < r1; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += H(i, c0 + j) * v[j];
+        s *= beta;
+        for (int j = 0; j < m; ++j) H(i, c0 + j) -= s * v[j];
+    }
+}
+
+// Plane rotation G = [[c, -s], [s, c]] on indices k, k+1 of an isolated
+// diagonal block: T <- G^T T G, U <- U G (full rows and columns; the entries
+// outside the quasi-triangular pattern that they touch are zero).
+void rotate(Mat& T, Mat& U, int k, double c, double s) {
+    const int n = T.n;
+    for (int j = 0; j < n; ++j) {  // rows: G^T
+        double x = T(k, j), y = T(k + 1, j);
+        T(k, j) = c * x + s * y;
+        T(k + 1, j) = -s * x + c * y;
+    }
+    for (int i = 0; i < n; ++i) {  // columns: G
+        double x = T(i, k), y = T(i, k + 1);
+        T(i, k) = c * x + s * y;
+        T(i, k + 1) = -s * x + c * y;
+        double ux = U(i, k), uy = U(i, k + 1);
+        U(i, k) = c * ux + s * uy;
+        U(i, k + 1) = -s * ux + c * uy;
+    }
+}
+
+// Standardise the 2x2 diagonal block at rows/columns k, k+1.
+void standardize_block(Mat& T, Mat& U, int k) {
+    const double a = T(k, k), b = T(k, k + 1), c = T(k + 1, k), d = T(k + 1, k + 1);
+    if (c == 0.0) return;
+    const double p = 0.5 * (a - d);
+    const double disc = p * p + b * c;
+    if (disc >= 0.0) {
+        // real eigenvalues: rotate an eigenvector onto e_1 -> upper triangular
+        const double sq = std::sqrt(disc);
+        const double lam = 0.5 * (a + d) + (p >= 0.0 ? sq : -sq);
+        double v1 = b, v2 = lam - a;        // from row 1: (a - lam) v1 + b v2 = 0
+        double w1 = lam - d, w2 = c;        // from row 2: c v1 + (d - lam) v2 = 0
+        if (std::hypot(w1, w2) > std::hypot(v1, v2)) {
+            v1 = w1;
+            v2 = w2;
+        }
+        const double r = std::hypot(v1, v2);
+        if (r == 0.0) return;
+        rotate(T, U, k, v1 / r, v2 / r);
+        T(k + 1, k) = 0.0;
+    } else {
+        // complex pair: equal diagonal entries,
+        // (a - d) cos 2t + (b + c) sin 2t = 0
+        const double th = 0.5 * std::atan2(-(a - d), b + c);
+        rotate(T, U, k, std::cos(th), std::sin(th));
+        const double m = 0.5 * (T(k, k) + T(k + 1, k + 1));
+        T(k, k) = m;
+        T(k + 1, k + 1) = m;
+    }
+}
+
+int schur_one(int n, const double* A, double* Tout, double* Uout, std::string& err) {
+    Mat H(n), U(n);
+    std::memcpy(H.a.data(), A, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) U(i, i) = 1.0;
+    for (double x : H.a)
+        if (!std::isfinite(x)) {
+            err = "coefficient matrix has a non-finite entry";
+            return TT_EINVAL;
+        }
+    std::vector<double> x((size_t)n + 3), v((size_t)n + 3);
+    // 1. Hessenberg reduction
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        for (int i = 0; i < m; ++i) x[i] = H(k + 1 + i, k);
+        const double beta = householder(x.data(), m, v.data());
+        apply_left(H, k + 1, m, k, n, v.data(), beta);
+        apply_right(H, k + 1, m, 0, n, v.data(), beta);
+        apply_right(U, k + 1, m, 0, n, v.data(), beta);
+        for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
+    }
+    // 2. Francis double-shift QR with deflation
+    const double eps = std::ldexp(1.0, -52);
+    double anorm = 0.0;
+    for (double x2 : H.a) anorm = std::fmax(anorm, std::fabs(x2));
+    int p = n - 1, iter = 0, total = 0;
+    while (p >= 1) {
+        int l = p;
+        while (l >= 1) {
+            double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
+            if (s == 0.0) s = anorm;
+            if (std::fabs(H(l, l - 1)) <= eps * s) {
+                H(l, l - 1) = 0.0;
+                break;
+            }
+            --l;
+        }
+        if (l == p) {  // 1x1 block converged
+            --p;
+            iter = 0;
+            continue;
+        }
+        if (l == p - 1) {  // 2x2 block converged
+            standardize_block(H, U, p - 1);
+            p -= 2;
+            iter = 0;
+            continue;
+        }
+        if (++total > 40 * n) {
+            err = "QR iteration did not converge";
+            return TT_EINVAL;
+        }
+        ++iter;
+        double s, t;
+        if (iter % 11 == 10) {  // exceptional shift
+            const double w = std::fabs(H(p, p - 1)) + std::fabs(H(p - 1, p - 2));
+            const double z = H(p, p) + 0.75 * w;
+            s = 2.0 * z;
+            t = z * z;
+        } else {
+            s = H(p - 1, p - 1) + H(p, p);
+            t = H(p - 1, p - 1) * H(p, p) - H(p - 1, p) * H(p, p - 1);
+        }
+        double xx = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
+        double yy = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
+        double zz = H(l + 1, l) * H(l + 2, l + 1);
+        for (int k = l; k <= p - 2; ++k) {
+            double xv[3] = {xx, yy, zz};
+            double vv[3];
+            const double beta = householder(xv, 3, vv);
+            const int q = (k > l) ? k - 1 : l;
+            apply_left(H, k, 3, q, n, vv, beta);
+            const int r = (k + 4 < p + 1) ? k + 4 : p + 1;
+            apply_right(H, k, 3, 0, r, vv, beta);
+            apply_right(U, k, 3, 0, n, vv, beta);
+            if (k > l) {
+                H(k + 1, k - 1) = 0.0;
+                H(k + 2, k - 1) = 0.0;
+            }
+            xx = H(k + 1, k);
+            yy = H(k + 2, k);
+            if (k < p - 2) zz = H(k + 3, k);
+        }
+        {
+            double xv[2] = {xx, yy};
+            double vv[2];
+            const double beta = householder(xv, 2, vv);
+            apply_left(H, p - 1, 2, p - 2, n, vv, beta);
+            apply_right(H, p - 1, 2, 0, p + 1, vv, beta);
+            apply_right(U, p - 1, 2, 0, n, vv, beta);
+            H(p, p - 2) = 0.0;
+        }
+    }
+    // 3. exact zeros below the quasi-triangular pattern
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j + 1 < i; ++j) H(i, j) = 0.0;
+    for (int i = 1; i < n; ++i)
+        if (H(i, i - 1) != 0.0 && i >= 2 && H(i - 1, i - 2) != 0.0) {
+            err = "internal: consecutive nonzero subdiagonals after QR";
+            return TT_EINVAL;
+        }
+    std::memcpy(Tout, H.a.data(), sizeof(double) * (size_t)n * n);
+    std::memcpy(Uout, U.a.data(), sizeof(double) * (size_t)n * n);
+    return TT_OK;
+}
+
+}  // namespace
+
+int schur_real(int n, const double* A, double* T, double* U, std::string& err) {
+    if (n <= 0) return TT_OK;
+    return schur_one(n, A, T, U, err);
+}
+
+// Several independent decompositions (one per mode) on host threads.
+int schur_real_many(int count, const int* n, const double* const* A, double* const* T, double* const* U,
+                    std::string& err) {
+    std::vector<int> rc((size_t)count, TT_OK);
+    std::vector<std::string> msg((size_t)count);
+    std::vector<std::thread> th;
+    for (int i = 0; i < count; ++i)
+        th.emplace_back([&, i] { rc[(size_t)i] = schur_real(n[i], A[i], T[i], U[i], msg[(size_t)i]); });
+    for (auto& t : th) t.join();
+    for (int i = 0; i < count; ++i)
+        if (rc[(size_t)i]) {
+            err = msg[(size_t)i];
+            return rc[(size_t)i];
+        }
+    return TT_OK;
+}
+
+}  // namespace tt

@@ -1,0 +1,270 @@
+"""Parity of the HIP pipelines around the triangular solve with the CPU
+oracle: dense coefficients (Algorithm 1: host Schur + GPU transforms), the
+pair form, the adjoint, and mixed precision with FP64 refinement."""
+import numpy as np
+import pytest
+
+import oracle
+import tt_inputs as ti
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def tt():
+    import paper_1905_09539_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ---------------------------------------------------------------- dense (a1, a2, a4)
+@pytest.mark.parametrize("shape,seed", [((24, 31, 17), 1), ((64, 64, 64), 2), ((50, 45), 3),
+                                        ((12, 9, 14, 11), 4), ((130,), 5), ((1, 7, 3), 6)])
+def test_general_matches_oracle(shape, seed):
+    p = ti.laplace_dense(shape, seed=seed)
+    print("case general", shape, seed, flush=True)
+    info = {}
+    X = host(tt().solve_general(p["A"], dev(p["B"]), info=info))
+    Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+    assert info["host_seconds"] >= 0
+
+
+def test_general_in_place():
+    p = ti.laplace_dense((33, 20, 27), seed=7)
+    B = dev(p["B"])
+    print("case general in place", flush=True)
+    tt().solve_general(p["A"], B, X=B)
+    Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
+    assert rel(host(B), Xo) <= TOL
+
+
+def test_general_full_size_residual():
+    """d = 3, n = 512 dense coefficients: the oracle takes minutes here, so
+    check the residual B - sum_mu X x_mu A_mu, evaluated with torch matmul
+    (independent of the library's kernels)."""
+    n = 512
+    p = ti.laplace_dense((n, n, n), seed=1)
+    print("case general 512^3", flush=True)
+    B = dev(p["B"])
+    X = tt().solve_general(p["A"], B)
+    A = [dev(a) for a in p["A"]]
+    R = B.clone()
+    R -= torch.matmul(A[0], X.reshape(n, n * n)).reshape(n, n, n)
+    R -= torch.matmul(A[1], X)
+    R -= torch.matmul(X, A[2].t().contiguous())
+    r = float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
+    assert r <= 1e-13
+
+
+# ---------------------------------------------------------------- pair form (a5)
+@pytest.mark.parametrize("shape,seed", [((9, 7, 12, 10), 1), ((5, 6, 4, 3), 2), ((13, 11, 17), 3)])
+def test_pair_matches_direct_oracle(shape, seed):
+    """Element-wise substitution on the pair operator (no reduction)."""
+    p = ti.pair_tri(shape, seed=seed)
+    print("case pair direct", shape, flush=True)
+    X = host(tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in p["C"]]))
+    Xo = oracle.pair_solve(p["A"], p["C"], p["B"], method="direct")
+    assert rel(X, Xo) <= TOL
+
+
+@pytest.mark.parametrize("shape,seed", [((24, 20, 16, 12), 4), ((96, 96, 96, 96), 5)])
+def test_pair_matches_reduced_oracle(shape, seed):
+    p = ti.pair_tri(shape, seed=seed)
+    print("case pair reduced", shape, flush=True)
+    X = host(tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in p["C"]]))
+    Xo = oracle.pair_solve(p["A"], p["C"], p["B"], method="reduced")
+    assert rel(X, Xo) <= TOL
+    if X.size <= 10 ** 6:
+        # residual of the pair operator (oracle's direct apply), independent
+        # of the reduction both sides use
+        r = oracle.pair_apply(p["A"], p["C"], X) - p["B"]
+        assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(p["B"])
+
+
+def test_pair_merge_case_corner():
+    """(1024, 1024, 8, 8): with triangular pairs, the solution on the far
+    corner box depends only on that box, so the corner is a smaller pair
+    problem the oracle solves directly."""
+    shape = (1024, 1024, 8, 8)
+    p = ti.pair_tri(shape, seed=6)
+    print("case pair 1024x1024x8x8", flush=True)
+    X = host(tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in p["C"]]))
+    lo = [1024 - 12, 1024 - 10, 0, 0]
+    for mu in range(2):
+        while lo[mu] > 0 and p["A"][mu][lo[mu], lo[mu] - 1] != 0.0:
+            lo[mu] -= 1
+    sl = tuple(slice(l, None) for l in lo)
+    A = [np.ascontiguousarray(a[l:, l:]) for a, l in zip(p["A"], lo)]
+    C = [np.ascontiguousarray(c[l:, l:]) for c, l in zip(p["C"], lo)]
+    Xo = oracle.pair_solve(A, C, np.ascontiguousarray(p["B"][sl]), method="direct")
+    assert rel(X[sl], Xo) <= TOL
+    assert np.all(np.isfinite(X))
+
+
+def test_pair_identity_C_is_laplace():
+    p = ti.pair_tri((20, 30, 25), seed=8)
+    C = [np.eye(a.shape[0]) for a in p["A"]]
+    print("case pair C=I", flush=True)
+    X = host(tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in C]))
+    Xo = oracle.lap_solve(p["A"], p["B"])
+    assert rel(X, Xo) <= 1e-14 * 100
+
+
+def test_pair_rejects_non_triangular_C():
+    p = ti.pair_tri((6, 5, 4), seed=9)
+    C = [c.copy() for c in p["C"]]
+    C[1][3, 1] = 0.5
+    with pytest.raises(tt().TTError):
+        tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in C])
+
+
+# ---------------------------------------------------------------- adjoint (a7)
+@pytest.mark.parametrize("shape,seed,dense", [((33, 20, 41), 1, False), ((17, 40, 9), 2, True),
+                                              ((12, 10, 8, 14), 3, False), ((70, 50), 4, False)])
+def test_backward_matches_oracle(shape, seed, dense):
+    p = ti.laplace_tri(shape, seed=seed, bumps="random")
+    G = ti.gaussian_tensor(shape, ti.rng(seed, ti.ROLE_G))
+    print("case backward", shape, dense, flush=True)
+    T = [dev(t) for t in p["T"]]
+    X = tt().solve_tri(T, dev(p["B"]))
+    dB, dT = tt().solve_backward(T, X, dev(G), dense_grad=dense)
+    Xh = host(X)
+    Lam = oracle.lap_solve(p["T"], G, trans=True)
+    assert rel(host(dB), Lam) <= TOL
+    for mu in range(len(shape)):
+        ref = oracle.grad_T(p["T"], Lam, Xh, mu, mask=not dense)
+        assert rel(host(dT[mu]), ref) <= TOL
+
+
+def test_backward_batched_uneven_full_size():
+    """64 problems with mode sizes uniform on {32..192} (uneven batch)."""
+    probs = ti.uneven_batch(64, 32, 192, seed=0)
+    print("case backward batch 64 uneven", flush=True)
+    T = [[dev(t) for t in q["T"]] for q in probs]
+    plan = tt().Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs])
+    Bs = [dev(q["B"]) for q in probs]
+    Xs = plan.solve(Bs)
+    plan.status()
+    dB, dT = tt().solve_backward_batched(T, Xs, [dev(q["G"]) for q in probs])
+    for b in (0, 17, 63):
+        q = probs[b]
+        Xo = oracle.lap_solve(q["T"], q["B"])
+        assert rel(host(Xs[b]), Xo) <= TOL
+        Lam = oracle.lap_solve(q["T"], q["G"], trans=True)
+        assert rel(host(dB[b]), Lam) <= TOL
+        for mu in range(3):
+            assert rel(host(dT[b][mu]), oracle.grad_T(q["T"], Lam, Xo, mu)) <= TOL
+    # every problem: adjoint identity <X, G> = <B, Lam>
+    for b, q in enumerate(probs):
+        lhs = float(torch.sum(Xs[b] * dev(q["G"])))
+        rhs = float(torch.sum(dev(q["B"]) * dB[b]))
+        assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0) * 10
+
+
+def test_autograd_function_gradcheck():
+    """Central finite differences (torch.autograd.gradcheck, h = 1e-6) on a
+    small problem, gradients w.r.t. B and the pattern entries of T."""
+    p = ti.laplace_tri((4, 5, 3), seed=5, bumps="random")
+    B = dev(p["B"]).requires_grad_(True)
+    T = [dev(t).requires_grad_(True) for t in p["T"]]
+    masks = [dev(ti.pattern_mask(t).astype(np.float64)) for t in p["T"]]
+    f = tt().TriTensorSolve
+
+    def fn(B, *Tv):
+        # only pattern entries are free parameters
+        return f.apply(B, *[tv * m for tv, m in zip(Tv, masks)])
+
+    print("case gradcheck", flush=True)
+    assert torch.autograd.gradcheck(fn, (B, *T), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_directional_fd_cfg4_size():
+    """Directional central differences (h = 1e-6) along 8 unit directions in B
+    and in the pattern of T, at a mode size of the uneven batch."""
+    shape = (64, 48, 80)
+    p = ti.laplace_tri(shape, seed=11)
+    G = ti.gaussian_tensor(shape, ti.rng(11, ti.ROLE_G))
+    Tg = [dev(t) for t in p["T"]]
+    B = dev(p["B"])
+    Gd = dev(G)
+    X = tt().solve_tri(Tg, B)
+    dB, dT = tt().solve_backward(Tg, X, Gd)
+    h = 1e-6
+    print("case directional fd", flush=True)
+    for k in range(4):
+        V = dev(ti.direction(shape, 11, k))
+        Lp = float(torch.sum(tt().solve_tri(Tg, B + h * V) * Gd))
+        Lm = float(torch.sum(tt().solve_tri(Tg, B - h * V) * Gd))
+        fd = (Lp - Lm) / (2 * h)
+        an = float(torch.sum(dB * V))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0)
+    for k in range(4):
+        mu = k % 3
+        m = ti.pattern_mask(p["T"][mu])
+        D = np.random.default_rng(100 + k).standard_normal(m.shape) * m
+        D /= np.linalg.norm(D)
+        Dg = dev(D)
+        Tp = [t.clone() for t in Tg]
+        Tm = [t.clone() for t in Tg]
+        Tp[mu] += h * Dg
+        Tm[mu] -= h * Dg
+        Lp = float(torch.sum(tt().solve_tri(Tp, B) * Gd))
+        Lm = float(torch.sum(tt().solve_tri(Tm, B) * Gd))
+        fd = (Lp - Lm) / (2 * h)
+        an = float(torch.sum(dT[mu] * Dg))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0)
+
+
+# ---------------------------------------------------------------- mixed precision (a6)
+@pytest.mark.parametrize("shape,seed", [((40, 40, 40), 1), ((96, 80, 72), 2)])
+def test_mixed_precision_general(shape, seed):
+    p = ti.laplace_dense(shape, seed=seed)
+    info = {}
+    print("case mp general", shape, flush=True)
+    X = host(tt().solve_general(p["A"], dev(p["B"]), prec=tt().TT_MP_FP32, tol=1e-13, info=info))
+    Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+    # an FP32-accurate inner solve gains about 7 digits per step
+    assert 1 <= info["iterations"] <= 4 and info["ratio"] <= 1e-13
+
+
+def test_mixed_precision_triangular():
+    p = ti.laplace_tri((50, 61, 47), seed=3)
+    info = {}
+    print("case mp tri", flush=True)
+    X = host(tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), prec=tt().TT_MP_FP32, info=info))
+    assert rel(X, oracle.lap_solve(p["T"], p["B"])) <= TOL
+    assert 1 <= info["iterations"] <= 4
+
+
+def test_mixed_precision_first_correction_is_fp32_sized():
+    """The low-precision solve really runs in FP32: the first correction is of
+    FP32 size relative to X, and one FP64 refinement step brings the error
+    far below it.  With max_iter = 1 and an unreachable tol the call reports
+    TT_ENOTCONV and leaves the refined X in place."""
+    p = ti.laplace_tri((64, 64, 64), seed=4)  # 4 leaf blocks per mode: FP32 updates occur
+    info = {}
+    X = torch.empty_like(dev(p["B"]))
+    print("case mp one step", flush=True)
+    with pytest.raises(tt().TTError) as e:
+        tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), X=X, prec=tt().TT_MP_FP32, tol=1e-300,
+                       max_iter=1, info=info)
+    assert e.value.code == tt().TT_ENOTCONV
+    assert info["iterations"] == 1
+    assert 1e-11 < info["ratio"] < 1e-4
+    assert rel(host(X), oracle.lap_solve(p["T"], p["B"])) <= 1e-9
