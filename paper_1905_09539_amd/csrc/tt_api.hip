@@ -73,6 +73,9 @@ struct tt_plan_s {
     // device
     ProbDesc* d_probs = nullptr;
     LeafDesc* d_leaves = nullptr;
+    LeafShape* d_shapes = nullptr;
+    uint16_t* d_ents = nullptr;
+    int32_t* d_hoffs = nullptr;
     UpdDesc* d_tasks = nullptr;
     WorkItem* d_items = nullptr;
     int* d_status = nullptr;
@@ -110,6 +113,9 @@ struct tt_plan_s {
         for (void* p : owned) (void)hipFree(p);
         if (d_probs) (void)hipFree(d_probs);
         if (d_leaves) (void)hipFree(d_leaves);
+        if (d_shapes) (void)hipFree(d_shapes);
+        if (d_ents) (void)hipFree(d_ents);
+        if (d_hoffs) (void)hipFree(d_hoffs);
         if (d_tasks) (void)hipFree(d_tasks);
         if (d_items) (void)hipFree(d_items);
         if (d_status) (void)hipFree(d_status);
@@ -249,6 +255,9 @@ int finish_plan(tt_plan_s* P, int nmin) {
     }
     if ((rc = upload(pd, &P->d_probs))) return rc;
     if ((rc = upload(s.leaves, &P->d_leaves))) return rc;
+    if ((rc = upload(s.shapes, &P->d_shapes))) return rc;
+    if ((rc = upload(s.ents, &P->d_ents))) return rc;
+    if ((rc = upload(s.hoffs, &P->d_hoffs))) return rc;
     if ((rc = upload(s.tasks, &P->d_tasks))) return rc;
     if ((rc = upload(s.items, &P->d_items))) return rc;
     if (hipMalloc((void**)&P->d_status, sizeof(int) * 4) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
@@ -293,8 +302,8 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
         const Wave& wv = s.waves[k];
         if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(st, P->evU[k - 1], 0));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->lb[k], st));
-        TT_HIP_CHECK(launch_leaf(s.D, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_status,
-                                 s.bmax, s.leaf_lds_bytes, st));
+        TT_HIP_CHECK(launch_leaf(s.D, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
+                                 P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH, st));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->la[k], st));
         TT_HIP_CHECK(hipEventRecord(P->evL[k], st));
         if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));

@@ -12,7 +12,8 @@
 namespace tt {
 
 constexpr int kMaxD = 4;          // internal order (d < 3 is promoted to 3)
-constexpr int kLeafThreads = 512; // one workgroup per leaf block
+constexpr int kLeafNT = 256;      // threads of the workgroup owning one leaf block
+constexpr int kMaxLeaf = 24;      // largest leaf block edge
 constexpr int kUpdThreads = 256;  // one workgroup per 64x64 update tile
 constexpr int kTile = 64;
 
@@ -34,6 +35,29 @@ struct LeafDesc {
     int32_t flags;               // bit mu: subtract accumulator A[mu];
                                  // bit 4+mu: the next block along mu exists
                                  // (its contribution is applied in the leaf)
+    int32_t shape;               // index of the tuple-grid shape (LeafShape)
+};
+
+// Hyperplane-ordered tuple list of one tuple-grid shape (m_0, ..., m_{D-1}
+// diagonal blocks per mode): entries ents[ent + hoffs[hoff + h] ...
+// ent + hoffs[hoff + h + 1]) are the tuples of hyperplane h, coordinates
+// packed in kTupBits(D) bits per mode.
+struct LeafShape {
+    int32_t ent, hoff, H, count;
+};
+constexpr int kTupBits3 = 5;     // D = 3: tuple coordinates < 32
+constexpr int kTupBits4 = 4;     // D = 4: tuple coordinates < 16
+
+// LDS geometry of the leaf kernel for the largest block of a launch.
+struct LeafGeom {
+    int cap;                     // prod bmax
+    int tsum;                    // sum bmax^2
+    int tamax;                   // max bmax^2
+    int maxtup;                  // largest tuple grid (entries)
+    int maxcpl;                  // most coupled tuples (a 2x2 block in some mode) of a leaf
+    int maxH;                    // most hyperplanes
+    int uwords;                  // doubles of the union region
+    int bm[kMaxD];
 };
 
 // One right-looking update of the dyadic recursion along mode mu:
@@ -106,20 +130,22 @@ struct Schedule {
     std::vector<Wave> waves;
     PlanStats stats;
     int bmax[kMaxD] = {1, 1, 1, 1};
-    int leaf_lds_bytes = 0;
+    std::vector<LeafShape> shapes;
+    std::vector<uint16_t> ents;
+    std::vector<int32_t> hoffs;
+    int maxtup = 1, maxcpl = 1, maxH = 1;
 };
 
 // Planner entry: problems must have D, n, stride, T filled.  Returns a
 // status and a message.
 int build_schedule(Schedule& s, int nmin, std::string& err);
-int leaf_lds_bytes(int D, const int* bmax);
-int leaf_pool_doubles(int D, const int* bmax);
+int leaf_lds_bytes(int D, const int* bmax, int maxtup, int maxcpl, int maxH);
 int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst, std::string& err);
 
 // Kernel launchers (tt_kernels.hip).
-hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count,
-                       const ProbDesc* probs, int* status, const int* bmax, int lds_bytes,
-                       hipStream_t st);
+hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
+                       const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
+                       const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st);
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
                          int64_t count, const ProbDesc* probs, int lp, hipStream_t st);
 hipError_t launch_zero_int(int* p, int count, hipStream_t st);

@@ -1,0 +1,709 @@
+// Leaf solve of the recursive triangular solve (gfx950).
+//
+// At the leaves of Algorithm 2 (size <= n_min per mode) the paper solves the
+// small Laplace-like system directly.  Here one workgroup (256 threads) owns
+// one leaf block B and
+//   1. loads the right-hand side X[B] - sum_{mu>=1} A_mu[B] (mode-0 updates
+//      were subtracted from X in place, the others wait in accumulators) and
+//      the diagonal blocks T_mu[B, B] into LDS;
+//   2. subtracts the contribution of the next block along each mode,
+//      T_mu[B, B+1] x_mu X[B+1] -- the update of the split between two
+//      adjacent leaves, which the schedule leaves to the leaf itself;
+//   3. partitions each mode of the block into the 1x1 / 2x2 diagonal blocks
+//      of the quasi-triangular T_mu and solves block back-substitution over
+//      the tuples of those blocks: tuples on one hyperplane of the tuple grid
+//      are independent, so each hyperplane is one parallel step.  In a step
+//      every unknown forms its right-hand side (one thread per unknown) and a
+//      tuple with widths w_mu couples its ne = prod w_mu unknowns by
+//      sum_mu I (x) T_mu[p_mu, p_mu] (x) I: ne = 1 is a division by the
+//      eigenvalue sum, larger tuples are small dense solves in registers;
+//   4. stores the solved block.
+// The hyperplane order of the tuple grid depends only on the number of tuples
+// per mode, so the planner precomputes one ordered list per grid shape.
+#include "tt_internal.h"
+
+namespace tt {
+
+namespace {
+
+// Gaussian elimination with partial pivoting on a small system held in
+// registers (all indices static).  Returns false on a zero pivot or a
+// non-finite result.
+template <int NE>
+__device__ inline bool gepp_small(double (&M)[NE][NE], double (&r)[NE]) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < NE; ++i) {
+            if (fabs(M[i][k]) > fabs(M[k][k])) {
+#pragma unroll
+                for (int j = 0; j < NE; ++j) {
+                    double t = M[k][j];
+                    M[k][j] = M[i][j];
+                    M[i][j] = t;
+                }
+                double t = r[k];
+                r[k] = r[i];
+                r[i] = t;
+            }
+        }
+        const double piv = M[k][k];
+        if (piv == 0.0) ok = false;
+#pragma unroll
+        for (int i = k + 1; i < NE; ++i) {
+            const double f = M[i][k] / piv;
+#pragma unroll
+            for (int j = k; j < NE; ++j) M[i][j] -= f * M[k][j];
+            r[i] -= f * r[k];
+        }
+    }
+#pragma unroll
+    for (int k = NE - 1; k >= 0; --k) {
+        double acc = r[k];
+#pragma unroll
+        for (int j = k + 1; j < NE; ++j) acc -= M[k][j] * r[j];
+        r[k] = acc / M[k][k];
+        if (!isfinite(r[k])) ok = false;
+    }
+    return ok;
+}
+
+// Matrix of a tuple with K = log2(NE) modes of width 2.  Dm[j] is the 2x2
+// diagonal block (row-major) of the j-th such mode in increasing mode order;
+// the last of them owns bit 0 of the local unknown index.  c is the sum of the
+// 1x1 diagonal entries of the other modes:  M = sum_j I (x) D_j (x) I + c I.
+template <int NE>
+__device__ inline void tuple_matrix(double (&M)[NE][NE], const double (&Dm)[4][4], double c) {
+    constexpr int K = (NE == 2) ? 1 : (NE == 4) ? 2 : (NE == 8) ? 3 : 4;
+#pragma unroll
+    for (int q = 0; q < NE; ++q)
+#pragma unroll
+        for (int q2 = 0; q2 < NE; ++q2) {
+            double m = (q == q2) ? c : 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int b = K - 1 - j;
+                if (((q ^ q2) & ~(1 << b)) == 0) m += Dm[j][((q >> b) & 1) * 2 + ((q2 >> b) & 1)];
+            }
+            M[q][q2] = m;
+        }
+}
+
+// 4 unknowns (2x2 blocks in two modes): with D_0 = [p q; r t] and
+// K = D_1 + c I, the splitting below reduces to two 2x2 solves (Cramer).
+__device__ inline bool tuple_solve4(const double (&Dm)[4][4], double c, double (&b)[4]) {
+    const double p = Dm[0][0], q = Dm[0][1], r = Dm[0][2], t = Dm[0][3];
+    const double k00 = Dm[1][0] + c, k01 = Dm[1][1], k10 = Dm[1][2], k11 = Dm[1][3] + c;
+    // S = K + tI, Q = S (K + pI) - q r I, rhs = S b0 - q b1
+    const double s00 = k00 + t, s11 = k11 + t;
+    const double q00 = s00 * (k00 + p) + k01 * k10 - q * r, q01 = s00 * k01 + k01 * (k11 + p);
+    const double q10 = k10 * (k00 + p) + s11 * k10, q11 = k10 * k01 + s11 * (k11 + p) - q * r;
+    const double y0 = s00 * b[0] + k01 * b[1] - q * b[2], y1 = k10 * b[0] + s11 * b[1] - q * b[3];
+    const double dq = q00 * q11 - q01 * q10;
+    const double x0 = (q11 * y0 - q01 * y1) / dq, x1 = (q00 * y1 - q10 * y0) / dq;
+    const double z0 = b[2] - r * x0, z1 = b[3] - r * x1;
+    const double ds = s00 * s11 - k01 * k10;
+    const double x2 = (s11 * z0 - k01 * z1) / ds, x3 = (s00 * z1 - k10 * z0) / ds;
+    b[0] = x0;
+    b[1] = x1;
+    b[2] = x2;
+    b[3] = x3;
+    return dq != 0.0 && ds != 0.0 && isfinite(x0) && isfinite(x1) && isfinite(x2) && isfinite(x3);
+}
+
+// 8 unknowns: with D_0 = [p q; r t] and K the 4x4 matrix of the other two
+// 2x2 modes (plus c I), the system splits into
+//   (K + pI) x0 + q x1 = b0,   r x0 + (K + tI) x1 = b1,
+// so  [(K + tI)(K + pI) - q r I] x0 = (K + tI) b0 - q b1  and
+//     (K + tI) x1 = b1 - r x0  (K + pI and K + tI commute).
+__device__ inline bool tuple_solve8(const double (&Dm)[4][4], double c, double (&b)[8]) {
+    double Km[4][4];
+    double D2[4][4] = {{Dm[1][0], Dm[1][1], Dm[1][2], Dm[1][3]},
+                       {Dm[2][0], Dm[2][1], Dm[2][2], Dm[2][3]},
+                       {0, 0, 0, 0},
+                       {0, 0, 0, 0}};
+    tuple_matrix<4>(Km, D2, c);
+    const double p = Dm[0][0], q = Dm[0][1], r = Dm[0][2], t = Dm[0][3];
+    double S[4][4], Q[4][4], rhs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) S[i][j] = Km[i][j] + (i == j ? t : 0.0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double acc = (i == j) ? -q * r : 0.0;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) acc += S[i][l] * (Km[l][j] + (l == j ? p : 0.0));
+            Q[i][j] = acc;
+        }
+        double acc = -q * b[4 + i];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) acc += S[i][l] * b[l];
+        rhs[i] = acc;
+    }
+    bool ok = gepp_small<4>(Q, rhs);
+    double rhs1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        b[i] = rhs[i];
+        rhs1[i] = b[4 + i] - r * rhs[i];
+    }
+    ok = gepp_small<4>(S, rhs1) && ok;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[4 + i] = rhs1[i];
+    return ok;
+}
+
+// 16 unknowns (2x2 blocks in four modes) by the same splitting along the
+// first block: K is the 8x8 matrix of the other three modes plus c I,
+//   [K^2 + (p + t) K + (p t - q r) I] x0 = (K + tI) b0 - q b1   (dense 8x8),
+//   (K + tI) x1 = b1 - r x0                                    (8 unknowns).
+__device__ inline bool tuple_solve16(const double (&Dm)[4][4], double c, double (&b)[16]) {
+    const double p = Dm[0][0], q = Dm[0][1], r = Dm[0][2], t = Dm[0][3];
+    double D3[4][4] = {{Dm[1][0], Dm[1][1], Dm[1][2], Dm[1][3]},
+                       {Dm[2][0], Dm[2][1], Dm[2][2], Dm[2][3]},
+                       {Dm[3][0], Dm[3][1], Dm[3][2], Dm[3][3]},
+                       {0, 0, 0, 0}};
+    double Q[8][8], rhs[8];
+    {
+        double K[8][8];
+        tuple_matrix<8>(K, D3, c);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                double acc = (p + t) * K[i][j] + (i == j ? p * t - q * r : 0.0);
+#pragma unroll
+                for (int l = 0; l < 8; ++l) acc = fma(K[i][l], K[l][j], acc);
+                Q[i][j] = acc;
+            }
+            double acc = t * b[i] - q * b[8 + i];
+#pragma unroll
+            for (int l = 0; l < 8; ++l) acc = fma(K[i][l], b[l], acc);
+            rhs[i] = acc;
+        }
+    }
+    bool ok = gepp_small<8>(Q, rhs);
+    double r8[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        b[i] = rhs[i];
+        r8[i] = b[8 + i] - r * rhs[i];
+    }
+    ok = tuple_solve8(D3, c + t, r8) && ok;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[8 + i] = r8[i];
+    return ok;
+}
+
+// Exact e / s for 0 <= e < 2^16 and s >= 1, from rs = 1.0f / s: the value
+// (e + 0.5) / s < 2^16 / s lies at least 0.5 / s from an integer, while the
+// float product is off by at most 2^-23 * 2^16 / s = 2^-7 / s.
+__device__ inline int qdiv(int e, float rs) { return (int)(((float)e + 0.5f) * rs); }
+
+constexpr int kLoadBatch = 8;
+
+// sum_{j < len} L[to + j] L[xo + j xs] along one fibre (LDS offsets in
+// doubles), four terms per step.  The T rows carry four zeros past their end
+// and the X index is clamped to the fibre, so the last step needs no masking.
+__device__ inline double lds_dot(const double* L, int to, int xo, int xs, int len) {
+    double a0 = 0.0, a1 = 0.0;
+    const int last = xo + (len - 1) * xs;
+    for (int j = 0; j < len; j += 4) {
+        const int x0 = xo + j * xs;
+        a0 = fma(L[to + j], L[x0], a0);
+        a1 = fma(L[to + j + 1], L[min(x0 + xs, last)], a1);
+        a0 = fma(L[to + j + 2], L[min(x0 + 2 * xs, last)], a0);
+        a1 = fma(L[to + j + 3], L[min(x0 + 3 * xs, last)], a1);
+    }
+    return a0 + a1;
+}
+
+// Small system of a tuple with 2x2 blocks in some modes (a: first rows,
+// w: widths); the right-hand sides of its unknowns are already in Xs.
+template <int D>
+__device__ inline bool coupled_solve(double* Xs, double* const (&Ts)[D], const int (&tp)[D], const int (&ls)[D],
+                                     const int (&a)[D], const int (&w)[D], int e0) {
+    int ne = 1;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) ne *= w[mu];
+    double cdiag = 0.0, Dm[4][4];
+    int kb = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Dm[j][v] = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const double* Tm = Ts[mu] + a[mu] * tp[mu] + a[mu];
+        if (w[mu] == 2) {
+            const double d0 = Tm[0], d1 = Tm[1], d2 = Tm[tp[mu]], d3 = Tm[tp[mu] + 1];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j == kb) {
+                    Dm[j][0] = d0;
+                    Dm[j][1] = d1;
+                    Dm[j][2] = d2;
+                    Dm[j][3] = d3;
+                }
+            ++kb;
+        } else {
+            cdiag += Tm[0];
+        }
+    }
+    constexpr int NEMAX = 1 << D;
+    int eq[NEMAX];
+    double rb[NEMAX];
+#pragma unroll
+    for (int q = 0; q < NEMAX; ++q) {
+        // unknown q: the last width-2 mode owns bit 0
+        int e = e0, rq = q;
+#pragma unroll
+        for (int mu = D - 1; mu >= 0; --mu) {
+            const int d = (w[mu] == 2) ? (rq & 1) : 0;
+            if (w[mu] == 2) rq >>= 1;
+            e += d * ls[mu];
+        }
+        eq[q] = e;
+        rb[q] = (q < ne) ? Xs[e] : 0.0;
+    }
+    bool ok = true;
+    if (ne == 2) {
+        const double m00 = Dm[0][0] + cdiag, m01 = Dm[0][1], m10 = Dm[0][2], m11 = Dm[0][3] + cdiag;
+        const double det = m00 * m11 - m01 * m10;
+        const double x0 = (m11 * rb[0] - m01 * rb[1]) / det;
+        const double x1 = (m00 * rb[1] - m10 * rb[0]) / det;
+        if (det == 0.0 || !isfinite(x0) || !isfinite(x1)) ok = false;
+        Xs[eq[0]] = x0;
+        Xs[eq[1]] = x1;
+    } else if (ne == 4) {
+        double r4[4] = {rb[0], rb[1], rb[2], rb[3]};
+        if (!tuple_solve4(Dm, cdiag, r4)) ok = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xs[eq[q]] = r4[q];
+    } else if (ne == 8) {
+        double r8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) r8[q] = rb[q];
+        if (!tuple_solve8(Dm, cdiag, r8)) ok = false;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) Xs[eq[q]] = r8[q];
+    } else {
+        if constexpr (D == 4) {  // 2x2 blocks in every mode
+            double r16[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) r16[q] = rb[q];
+            if (!tuple_solve16(Dm, cdiag, r16)) ok = false;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Xs[eq[q]] = r16[q];
+        }
+    }
+    return ok;
+}
+
+}  // namespace
+
+// Three workgroups of four waves share a CU (LDS of a 16^3 leaf is ~50 KB),
+// so the order-3 kernel is held to three waves per SIMD worth of registers;
+// order 4 keeps its 16-unknown tuple solve in registers (one wave per SIMD).
+template <int D>
+__global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 : 3))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
+                                                      const ProbDesc* __restrict__ probs,
+                                                      const LeafShape* __restrict__ shapes,
+                                                      const uint16_t* __restrict__ ents,
+                                                      const int32_t* __restrict__ hoffs, int* status,
+                                                      LeafGeom geom) {
+    extern __shared__ double lds[];
+    const int tid = threadIdx.x;
+    const LeafDesc L = leaves[first + blockIdx.x];
+    const ProbDesc& P = probs[L.prob];
+
+    int r0[D], sz[D], ls[D], nx[D];
+    int64_t gs[D];
+    float rsz[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const int b = L.blk[mu];
+        r0[mu] = P.bst[mu][b];
+        const int r1 = P.bst[mu][b + 1];
+        sz[mu] = r1 - r0[mu];
+        nx[mu] = ((L.flags >> (4 + mu)) & 1) ? P.bst[mu][b + 2] - r1 : 0;
+        gs[mu] = P.stride[mu];
+        rsz[mu] = 1.0f / (float)sz[mu];
+    }
+    ls[D - 1] = 1;
+#pragma unroll
+    for (int mu = D - 2; mu >= 0; --mu) ls[mu] = ls[mu + 1] * sz[mu + 1];
+    const int cap = ls[0] * sz[0];
+
+    // LDS: Xs | Ts (diagonal blocks, row pitch sz + 4, zero padded) | union
+    // {adjacent T block; element records + coupled-tuple list} | per-mode
+    // bit tables | offsets
+    double* Xs = lds;
+    double* Ts[D];
+    int toff[D], tp[D];  // offsets of Ts[mu] from lds (doubles), row pitch
+    {
+        int o = geom.cap;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            Ts[mu] = lds + o;
+            toff[mu] = o;
+            tp[mu] = sz[mu] + 4;
+            o += geom.bm[mu] * (geom.bm[mu] + 4);
+        }
+    }
+    double* Ta = lds + geom.cap + geom.tsum;
+    uint16_t* rec = (uint16_t*)Ta;                         // geom.cap element records
+    uint16_t* clist = rec + geom.cap;                      // geom.maxcpl coupled tuples
+    uint64_t* rbits = (uint64_t*)(Ta + geom.uwords);       // row -> 2 bits: gap - 1, width - 1
+    uint32_t* tbits = (uint32_t*)(rbits + D);              // tuple -> 1 bit: width - 1
+    int32_t* hof = (int32_t*)(tbits + D + (D & 1));        // tuple offsets per hyperplane
+    int32_t* eoff = hof + geom.maxH + 1;                   // element offsets per hyperplane
+    int32_t* coff = eoff + geom.maxH + 1;                  // coupled-tuple offsets per hyperplane
+    int32_t* wsum = coff + geom.maxH + 1;                  // wave totals of the block scan
+    const LeafShape sh = shapes[L.shape];
+    for (int i = tid; i <= sh.H; i += kLeafNT) hof[i] = hoffs[sh.hoff + i];
+
+    double* __restrict__ X = P.X;
+    int64_t gbase = 0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) gbase += (int64_t)r0[mu] * gs[mu];
+
+    // local element index -> global offset (relative to gbase)
+    auto goff = [&](int e) {
+        int64_t g = 0;
+#pragma unroll
+        for (int mu = D - 1; mu >= 1; --mu) {
+            const int q = qdiv(e, rsz[mu]);
+            g += (int64_t)(e - q * sz[mu]) * gs[mu];
+            e = q;
+        }
+        return g + (int64_t)e * gs[0];
+    };
+
+    // ---- 1. right-hand side and diagonal blocks
+    for (int base = 0; base < cap; base += kLeafNT * kLoadBatch) {
+        double v[kLoadBatch];
+        int64_t g[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int e = base + u * kLeafNT + tid;
+            g[u] = (e < cap) ? gbase + goff(e) : -1;
+            v[u] = (g[u] >= 0) ? X[g[u]] : 0.0;
+        }
+#pragma unroll
+        for (int mu = 1; mu < D; ++mu) {
+            if (!((L.flags >> mu) & 1)) continue;  // uniform
+            const double* __restrict__ A = P.A[mu];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u)
+                if (g[u] >= 0) v[u] -= A[g[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int e = base + u * kLeafNT + tid;
+            if (e < cap) Xs[e] = v[u];
+        }
+    }
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const double* T = P.T[mu];
+        const int64_t n = P.n[mu];
+        const float rtp = 1.0f / (float)tp[mu];
+        for (int e = tid; e < sz[mu] * tp[mu]; e += kLeafNT) {
+            const int i = qdiv(e, rtp), j = e - i * tp[mu];
+            Ts[mu][e] = (j < sz[mu]) ? T[(int64_t)(r0[mu] + i) * n + r0[mu] + j] : 0.0;
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. 1x1 / 2x2 diagonal blocks of every mode (thread mu scans its block)
+    if (tid < D) {
+        const int mu = tid;
+        int m = sz[0], t0 = toff[0], pt = tp[0];
+#pragma unroll
+        for (int nu = 1; nu < D; ++nu)
+            if (nu == mu) {
+                m = sz[nu];
+                t0 = toff[nu];
+                pt = tp[nu];
+            }
+        int p = 0, i = 0;
+        uint64_t rb = 0;
+        uint32_t tb = 0;
+        while (i < m) {
+            const int w = (i + 1 < m && lds[t0 + (i + 1) * pt + i] != 0.0) ? 2 : 1;
+            if (w == 2) {
+                rb |= (uint64_t)3 << (2 * i) | (uint64_t)2 << (2 * i + 2);  // gap 2 / 1, width 2
+                tb |= 1u << p;
+            }
+            i += w;
+            ++p;
+        }
+        rbits[mu] = rb;
+        tbits[mu] = tb;
+    }
+
+    // ---- 3. contributions of the next block along each mode
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const int nxm = nx[mu];
+        if (nxm == 0) continue;  // uniform over the workgroup
+        const double* T = P.T[mu];
+        const int64_t n = P.n[mu];
+        const int r1 = r0[mu] + sz[mu];
+        for (int e = tid; e < sz[mu] * nxm; e += kLeafNT) {
+            const int i = e / nxm, j = e - (e / nxm) * nxm;
+            Ta[e] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
+        }
+        __syncthreads();
+        // one thread per fibre along mu
+        const int F = cap / sz[mu];
+        const int64_t nstep = (int64_t)sz[mu] * gs[mu];  // from row r0+i to row r1+i
+        for (int f = tid; f < F; f += kLeafNT) {
+            int eb = 0;
+            int64_t gb = gbase;
+            {
+                int rem = f;
+#pragma unroll
+                for (int nu = D - 1; nu >= 0; --nu) {
+                    if (nu == mu) continue;
+                    const int q = qdiv(rem, rsz[nu]);
+                    const int c = rem - q * sz[nu];
+                    rem = q;
+                    eb += c * ls[nu];
+                    gb += (int64_t)c * gs[nu];
+                }
+            }
+            // the fibre of the next block, eight rows at a time in registers
+            // (clamped loads, zeroed past nxm); one row of T_mu[B, B+1] per
+            // output element
+            for (int jc = 0; jc < nxm; jc += 8) {
+                double xn[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool v = jc + j < nxm;
+                    const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
+                    xn[j] = v ? x : 0.0;
+                }
+                for (int i = 0; i < sz[mu]; ++i) {
+                    const double* ti = Ta + i * nxm + jc;
+                    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                    for (int j = 0; j < 8; j += 2) {
+                        const double t0 = (jc + j < nxm) ? ti[(jc + j < nxm) ? j : 0] : 0.0;
+                        const double t1 = (jc + j + 1 < nxm) ? ti[(jc + j + 1 < nxm) ? j + 1 : 0] : 0.0;
+                        a0 = fma(t0, xn[j], a0);
+                        a1 = fma(t1, xn[j + 1], a1);
+                    }
+                    Xs[eb + i * ls[mu]] -= a0 + a1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();  // tables of step 2 visible, Ta free
+    uint64_t rowbits[D];
+    uint32_t tupbits[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        rowbits[mu] = rbits[mu];
+        tupbits[mu] = tbits[mu];
+    }
+
+    // ---- 4. element lists: the shape's tuples expanded to their unknowns,
+    // hyperplane by hyperplane, and the coupled tuples (block-wide scan)
+    constexpr int kBits = (D == 4) ? kTupBits4 : kTupBits3;
+    constexpr int kCB = 16 / D;  // bits of a row index in an element record
+    // tuple p of mode mu starts at row p + (number of 2x2 blocks before it)
+    auto decode = [&](uint32_t en, int* a, int* w) {
+        int ne = 1;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            const int p = (en >> (kBits * mu)) & ((1 << kBits) - 1);
+            a[mu] = p + __popc(tupbits[mu] & ((1u << p) - 1u));
+            w[mu] = 1 + ((tupbits[mu] >> p) & 1);
+            ne *= w[mu];
+        }
+        return ne;
+    };
+    {
+        const int per = (sh.count + kLeafNT - 1) / kLeafNT;
+        const int t0 = min(sh.count, tid * per), t1 = min(sh.count, t0 + per);
+        auto entry = [&](int t) -> uint32_t { return ents[sh.ent + t]; };
+        int cnt = 0;  // elements | coupled tuples << 16
+        for (int t = t0; t < t1; ++t) {
+            int a[D], w[D];
+            const int ne = decode(entry(t), a, w);
+            cnt += ne + ((ne > 1) ? (1 << 16) : 0);
+        }
+        // exclusive block scan: wave scan by shuffles, then wave totals
+        const int lane = tid & 63, wv = tid >> 6;
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += v;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        int before = 0;
+        for (int k = 0; k < wv; ++k) before += wsum[k];
+        int on = (before + inc - cnt) & 0xffff, oc = (before + inc - cnt) >> 16;
+        int h = 0, hnext = 0;
+        if (t0 < t1) {
+            int lo = 0, hi = sh.H;  // hof[lo] <= t0 < hof[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (hof[mid] <= t0) lo = mid; else hi = mid;
+            }
+            h = lo;
+            hnext = hof[h + 1];
+            if (hof[h] == t0) {
+                eoff[h] = on;
+                coff[h] = oc;
+            }
+        }
+        for (int t = t0; t < t1; ++t) {
+            if (t == hnext) {  // first tuple of the next hyperplane(s)
+                while (hof[h + 1] <= t) ++h;
+                hnext = hof[h + 1];
+                eoff[h] = on;
+                coff[h] = oc;
+            }
+            const uint32_t e = entry(t);
+            int a[D], w[D];
+            const int ne = decode(e, a, w);
+            for (int q = 0; q < ne; ++q) {
+                // unknown q: the last width-2 mode owns bit 0
+                uint32_t r = 0;
+                int rq = q;
+#pragma unroll
+                for (int mu = D - 1; mu >= 0; --mu) {
+                    const int d = (w[mu] == 2) ? (rq & 1) : 0;
+                    if (w[mu] == 2) rq >>= 1;
+                    r |= (uint32_t)(a[mu] + d) << (kCB * mu);
+                }
+                rec[on++] = (uint16_t)r;
+            }
+            if (ne > 1) clist[oc++] = (uint16_t)e;
+        }
+        if (tid == kLeafNT - 1) {
+            eoff[sh.H] = on;
+            coff[sh.H] = oc;
+        }
+    }
+    __syncthreads();
+
+    // ---- 5. block back-substitution, one tuple hyperplane per step:
+    // (A) every unknown forms its right-hand side (unknowns of 1x1 tuples
+    // also divide by their eigenvalue sum), (B) coupled tuples solve their
+    // small systems
+    bool ok = true;
+    for (int h = 0; h < sh.H; ++h) {
+        const int ebeg = eoff[h], eend = eoff[h + 1];
+        for (int i = ebeg + tid; i < eend; i += kLeafNT) {
+            const uint32_t r = rec[i];
+            int c[D], e = 0;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) {
+                c[mu] = (r >> (kCB * mu)) & ((1 << kCB) - 1);
+                e += c[mu] * ls[mu];
+            }
+            double cd = 0.0, acc = 0.0;
+            bool single = true;
+#pragma unroll
+            for (int mu = 0; mu < D; ++mu) {
+                const int b2 = (int)(rowbits[mu] >> (2 * c[mu])) & 3;
+                const int gap = 1 + (b2 & 1);
+                single = single && !(b2 & 2);
+                const int dg = toff[mu] + c[mu] * (tp[mu] + 1);
+                cd += lds[dg];
+                acc += lds_dot(lds, dg + gap, e + gap * ls[mu], ls[mu], sz[mu] - c[mu] - gap);
+            }
+            const double rhs = lds[e] - acc;
+            if (single) {
+                const double x = rhs / cd;
+                if (cd == 0.0 || !isfinite(x)) ok = false;
+                lds[e] = x;
+            } else {
+                lds[e] = rhs;
+            }
+        }
+        const int cbeg = coff[h], cend = coff[h + 1];
+        if (cend > cbeg) {  // uniform
+            __syncthreads();
+            for (int k = cbeg + tid; k < cend; k += kLeafNT) {
+                int a[D], w[D];
+                decode(clist[k], a, w);
+                int e0 = 0;
+#pragma unroll
+                for (int mu = 0; mu < D; ++mu) e0 += a[mu] * ls[mu];
+                if (!coupled_solve<D>(Xs, Ts, tp, ls, a, w, e0)) ok = false;
+            }
+        }
+        __syncthreads();
+    }
+    if (!ok) atomicOr(status, 1);
+
+    // ---- 6. store the solved block
+    for (int base = 0; base < cap; base += kLeafNT * kLoadBatch) {
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int e = base + u * kLeafNT + tid;
+            if (e < cap) X[gbase + goff(e)] = Xs[e];
+        }
+    }
+}
+
+LeafGeom leaf_geometry(int D, const int* bmax, int maxtup, int maxcpl, int maxH) {
+    LeafGeom g{};
+    g.maxtup = maxtup;
+    g.maxcpl = maxcpl;
+    g.maxH = maxH;
+    g.cap = 1;
+    for (int mu = 0; mu < kMaxD; ++mu) g.bm[mu] = (mu < D) ? bmax[mu] : 1;
+    for (int mu = 0; mu < D; ++mu) {
+        g.cap *= bmax[mu];
+        g.tsum += bmax[mu] * (bmax[mu] + 4);
+        g.tamax = std::max(g.tamax, bmax[mu] * bmax[mu]);
+    }
+    // union of the adjacent block (doubles) and the element records plus the
+    // coupled-tuple list (u16 each)
+    g.uwords = std::max(g.tamax, ((g.cap + maxcpl) * 2 + 7) / 8);
+    return g;
+}
+
+int leaf_lds_bytes(int D, const int* bmax, int maxtup, int maxcpl, int maxH) {
+    const LeafGeom g = leaf_geometry(D, bmax, maxtup, maxcpl, maxH);
+    return (g.cap + g.tsum + g.uwords + D) * (int)sizeof(double) + (D + 1) * (int)sizeof(uint32_t) +
+           (3 * (maxH + 1) + kLeafNT / 64) * (int)sizeof(int32_t);
+}
+
+hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
+                       const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
+                       const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int lds = leaf_lds_bytes(D, bmax, maxtup, maxcpl, maxH);
+    const LeafGeom geom = leaf_geometry(D, bmax, maxtup, maxcpl, maxH);
+    dim3 grid((unsigned)count), block(kLeafNT);
+    if (lds > 64 * 1024) {
+        hipError_t e = (D == 3) ? hipFuncSetAttribute((const void*)leaf_kernel<3>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+                                : hipFuncSetAttribute((const void*)leaf_kernel<4>,
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    if (D == 3)
+        hipLaunchKernelGGL(leaf_kernel<3>, grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs, status,
+                           geom);
+    else
+        hipLaunchKernelGGL(leaf_kernel<4>, grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs, status,
+                           geom);
+    return hipGetLastError();
+}
+
+}  // namespace tt

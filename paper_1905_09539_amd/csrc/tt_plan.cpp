@@ -20,9 +20,11 @@
 // is solved.  At that moment all of R1 is solved and no block of R0 is, so
 // the update is exactly the one of Algorithm 2, restricted to one pencil.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 
 #include "tt_internal.h"
 
@@ -49,28 +51,98 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
             return TT_EINVAL;
         }
     // m = ceil(n / b) blocks of near-equal size (at most b rows), each ideal
-    // boundary moved to the previous row when it would cut a 2x2 block, so
-    // blocks have at most b + 1 rows.  Algorithm 2 moves k to k + 1 instead;
+    // boundary moved by one row when it would cut a 2x2 block (to the next
+    // row as Algorithm 2 does if that keeps the block within b rows, else to
+    // the previous one).  Algorithm 2 moves k to k + 1 instead;
     // any split with A(k+1, k) = 0 is valid (Sec. 2.1).
     auto cuts_bump = [&](int64_t k) { return k > 0 && k < n && T[k * n + k - 1] != 0.0; };
+    auto split = [&](int64_t m) {
+        bst.clear();
+        bst.push_back(0);
+        int big = 0;
+        for (int64_t k = 1; k < m; ++k) {
+            int64_t q = (k * n + m / 2) / m;
+            if (cuts_bump(q)) q = (q + 1 - bst.back() <= b && q + 1 < n) ? q + 1 : q - 1;
+            if (q <= bst.back()) continue;
+            big = std::max(big, (int)(q - bst.back()));
+            bst.push_back((int32_t)q);
+        }
+        big = std::max(big, (int)(n - bst.back()));
+        bst.push_back((int32_t)n);
+        return big;
+    };
+    // one more block when a moved boundary leaves a block over b rows
     const int64_t m = (n + b - 1) / b;
-    bst.push_back(0);
-    for (int64_t k = 1; k < m; ++k) {
-        int64_t q = (k * n + m / 2) / m;
-        if (cuts_bump(q)) --q;
-        if (q <= bst.back()) continue;
-        bst.push_back((int32_t)q);
-    }
-    bst.push_back((int32_t)n);
+    if (split(m) > b && m + 1 <= n) split(m + 1);
     for (size_t i = 0; i + 1 < bst.size(); ++i)
-        if (bst[i + 1] - bst[i] > 32) {
-            err = "leaf block larger than 32 rows; use nmin <= 20";
+        if (bst[i + 1] - bst[i] > kMaxLeaf) {
+            err = "leaf block larger than " + std::to_string(kMaxLeaf) + " rows; use a smaller nmin";
             return TT_EINVAL;
         }
     return TT_OK;
 }
 
 static inline int lowbit(int c) { return c & (-c); }
+
+// Number of 1x1 / 2x2 diagonal blocks of T (n x n, row-major) in rows
+// [r0, r1), and how many of them are 1x1.
+static int tuple_count(const std::vector<double>& T, int64_t n, int64_t r0, int64_t r1, int* ones) {
+    int m = 0, o = 0;
+    for (int64_t i = r0; i < r1; ++m) {
+        const bool two = i + 1 < r1 && T[(size_t)((i + 1) * n + i)] != 0.0;
+        o += two ? 0 : 1;
+        i += two ? 2 : 1;
+    }
+    *ones = o;
+    return m;
+}
+
+// Index of the tuple-grid shape (m_0, ..., m_{D-1}), creating its
+// hyperplane-ordered tuple list on first use.  Tuple p depends on the tuples
+// that are larger in one coordinate and equal in the others, so hyperplane
+// h = sum_mu (m_mu - 1 - p_mu) only depends on hyperplanes < h.
+static int32_t shape_index(Schedule& s, std::map<std::array<int, kMaxD>, int32_t>& known,
+                           const std::array<int, kMaxD>& m) {
+    auto it = known.find(m);
+    if (it != known.end()) return it->second;
+    const int D = s.D;
+    int H = 1, total = 1;
+    for (int mu = 0; mu < D; ++mu) {
+        H += m[mu] - 1;
+        total *= m[mu];
+    }
+    const int bits = (D == 4) ? kTupBits4 : kTupBits3;
+    std::vector<std::vector<uint16_t>> byh((size_t)H);
+    for (int lin = 0; lin < total; ++lin) {
+        int rem = lin, h = 0;
+        uint32_t ent = 0;
+        for (int mu = D - 1; mu >= 0; --mu) {
+            const int p = rem % m[mu];
+            rem /= m[mu];
+            h += m[mu] - 1 - p;
+            ent |= (uint32_t)p << (bits * mu);
+        }
+        byh[(size_t)h].push_back((uint16_t)ent);
+    }
+    LeafShape sh{};
+    sh.ent = (int32_t)s.ents.size();
+    sh.hoff = (int32_t)s.hoffs.size();
+    sh.H = H;
+    sh.count = total;
+    int off = 0;
+    for (int h = 0; h < H; ++h) {
+        s.hoffs.push_back(off);
+        for (uint16_t e : byh[(size_t)h]) s.ents.push_back(e);
+        off += (int)byh[(size_t)h].size();
+    }
+    s.hoffs.push_back(off);
+    s.maxtup = std::max(s.maxtup, total);
+    s.maxH = std::max(s.maxH, H);
+    const int32_t idx = (int32_t)s.shapes.size();
+    s.shapes.push_back(sh);
+    known[m] = idx;
+    return idx;
+}
 
 int build_schedule(Schedule& s, int nmin, std::string& err) {
     const int D = s.D;
@@ -81,6 +153,13 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
         return TT_EINVAL;
     }
     for (int mu = 0; mu < kMaxD; ++mu) s.bmax[mu] = 1;
+    s.shapes.clear();
+    s.ents.clear();
+    s.hoffs.clear();
+    s.maxtup = 1;
+    s.maxcpl = 1;
+    s.maxH = 1;
+    std::map<std::array<int, kMaxD>, int32_t> known_shapes;
     s.leaves.clear();
     s.tasks.clear();
     s.items.clear();
@@ -245,10 +324,18 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             int I[kMaxD];
             for (int mu = 0; mu < D; ++mu) I[mu] = L.blk[mu];
             L.flags = 0;
+            std::array<int, kMaxD> tm = {1, 1, 1, 1};
+            int all = 1, single = 1;
             for (int mu = 0; mu < D; ++mu) {
                 if (mu > 0 && received[(size_t)L.prob][(size_t)(block_lin(p, I) * D + mu)]) L.flags |= 1 << mu;
                 if (I[mu] + 1 < p.m[mu]) L.flags |= 1 << (4 + mu);
+                int ones = 0;
+                tm[mu] = tuple_count(p.T[mu], p.n[mu], p.bst[mu][I[mu]], p.bst[mu][I[mu] + 1], &ones);
+                all *= tm[mu];
+                single *= ones;
             }
+            s.maxcpl = std::max(s.maxcpl, all - single);
+            L.shape = shape_index(s, known_shapes, tm);
             s.leaves.push_back(L);
             // algorithmic work: in-block back-substitution + the adjacent blocks
             int64_t sz[kMaxD], ne = 1;
@@ -283,8 +370,12 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             for (int32_t tid : triggered[(size_t)(w - 1)]) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
                 const bool right = (t.mode == D - 1);
-                const int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
-                const int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
+                int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
+                int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
+                if (t.M <= 16) {  // wide tiles: 16 target rows x 256 pencil columns
+                    na = (t.P + 4 * kTile - 1) / (4 * kTile);
+                    nb = 1;
+                }
                 for (int a = 0; a < na; ++a)
                     for (int b = 0; b < nb; ++b) s.items.push_back(WorkItem{tid, (int16_t)a, (int16_t)b});
                 const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
@@ -302,21 +393,13 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
         return TT_EINVAL;
     }
 
-    // tuple slots within one hyperplane are packed in 11 bits
-    int emax = 2;
-    for (int mu = 0; mu < D - 1; ++mu) emax *= s.bmax[mu];
-    if (emax > 2047) {
-        err = "leaf block too large for the hyperplane lists; lower nmin";
-        return TT_EINVAL;
-    }
-    if (D == 4)
-        for (int mu = 0; mu < D; ++mu)
-            if (s.bmax[mu] > 16) {
-                err = "order-4 leaf blocks must have at most 16 rows per mode; lower nmin";
-                return TT_EINVAL;
-            }
-    s.leaf_lds_bytes = leaf_lds_bytes(D, s.bmax);
-    if (s.leaf_lds_bytes > 160 * 1024 || leaf_pool_doubles(D, s.bmax) < 0) {
+    for (int mu = 0; mu < D; ++mu)
+        if (s.bmax[mu] > ((D == 4) ? (1 << kTupBits4) : kMaxLeaf)) {
+            err = "leaf block too large (at most " + std::to_string(D == 4 ? (1 << kTupBits4) : kMaxLeaf) +
+                  " rows per mode); lower nmin";
+            return TT_EINVAL;
+        }
+    if (leaf_lds_bytes(D, s.bmax, s.maxtup, s.maxcpl, s.maxH) > 160 * 1024) {
         err = "leaf block does not fit in LDS; lower nmin";
         return TT_EINVAL;
     }

@@ -55,8 +55,10 @@ def test_partition_never_cuts_a_bump():
     n = 512
     p = ti.laplace_tri((n, n, n), seed=1, bumps="every8")
     info = tt.schedule_info(p["T"], (n, n, n))
-    # every 8th row starts a bump, so 16-row blocks must grow to 17
-    assert info["bmax0"] == 17 and info["waves"] == 94
+    # every 8th row starts a bump, so 32 blocks of 16 rows are impossible:
+    # the planner takes 33 blocks of at most 16 rows (3 * 32 + 1 waves)
+    assert info["bmax0"] == 16 and info["waves"] == 97
+    assert info["dependency_violation"] == 0
 
 
 def test_schedule_rejects_bad_structure():
