@@ -50,6 +50,110 @@ def cpu_baseline(n, seed, cores):
                       f"({F:.3e} flops in {dt:.2f} s)"}
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _residual(A, X, B):
+    """||B - sum_mu X x_mu A_mu||_F / ||B||_F with torch matmul (d = 3)."""
+    import torch
+    n0, n1, n2 = X.shape
+    R = B.clone()
+    R -= torch.matmul(A[0], X.reshape(n0, n1 * n2)).reshape(n0, n1, n2)
+    R -= torch.matmul(A[1], X)
+    R -= torch.matmul(X, A[2].t().contiguous())
+    return float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
+
+
+def extras(args):
+    """The other workloads of the method, timed the same way (inputs resident
+    in HBM, HIP events on the caller's stream)."""
+    import torch
+
+    import paper_1905_09539_amd as tt
+    import tt_inputs as ti
+    out = {}
+    steps = max(2, args.steps // 4)
+
+    # dense coefficients, d = 3, n = 512 (Algorithm 1: transforms + solve)
+    n = 512
+    p = ti.laplace_dense((n, n, n), seed=args.seed)
+    B = torch.from_numpy(p["B"]).cuda()
+    X = torch.empty_like(B)
+    plan = tt.Plan(p["A"], B.shape, general=True)
+    ms = _timed(lambda: plan.solve(B, X), steps, 1)
+    plan.status()
+    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+    out["dense_512"] = {"ms": ms, "tflops": plan.flops / (ms * 1e-3) / 1e12, "flops": plan.flops,
+                        "host_schur_s": plan.info()["schur_seconds"], "residual": _residual(Ad, X, B)}
+    del plan, B, X, Ad, p
+    torch.cuda.empty_cache()
+
+    # mixed precision vs FP64, d = 3, n = 768, eigenvalue sums in [3, 6]
+    n = 768
+    p = ti.laplace_dense((n, n, n), seed=args.seed)
+    B = torch.from_numpy(p["B"]).cuda()
+    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+    X64 = torch.empty_like(B)
+    Xmp = torch.empty_like(B)
+    plan64 = tt.Plan(p["A"], B.shape, general=True)
+    ms64 = _timed(lambda: plan64.solve(B, X64), 2, 1)
+    plan64.status()
+    r64 = _residual(Ad, X64, B)
+    del plan64
+    torch.cuda.empty_cache()
+    planmp = tt.Plan(p["A"], B.shape, general=True, prec=tt.TT_MP_FP32, tol=1e-13)
+    msmp = _timed(lambda: planmp.solve(B, Xmp), 2, 1)
+    planmp.status()
+    info = planmp.info()
+    rmp = _residual(Ad, Xmp, B)
+    diff = float(torch.linalg.vector_norm(Xmp - X64) / torch.linalg.vector_norm(X64))
+    out["mixed_768"] = {"ms_fp64": ms64, "ms_mp_fp32": msmp, "speedup": ms64 / msmp,
+                        "iterations": info["iterations"], "last_ratio": info["ratio"],
+                        "residual_fp64": r64, "residual_mp": rmp, "rel_diff_mp_vs_fp64": diff}
+    del planmp, B, Ad, X64, Xmp, p
+    torch.cuda.empty_cache()
+
+    # pair form, d = 4: (96, 96, 96, 96) and the merge case (1024, 1024, 8, 8)
+    for shp in [(96, 96, 96, 96), (1024, 1024, 8, 8)]:
+        p = ti.pair_tri(shp, seed=args.seed)
+        A = [torch.from_numpy(a).cuda() for a in p["A"]]
+        C = [torch.from_numpy(c).cuda() for c in p["C"]]
+        B = torch.from_numpy(p["B"]).cuda()
+        X = torch.empty_like(B)
+        plan = tt.Plan(A, B.shape, C=C)
+        ms = _timed(lambda: plan.solve(B, X), steps, 1)
+        plan.status()
+        out["pair_" + "x".join(str(x) for x in shp)] = {"ms": ms, "flops": plan.flops,
+                                                         "tflops": plan.flops / (ms * 1e-3) / 1e12}
+        del plan, A, C, B, X, p
+        torch.cuda.empty_cache()
+
+    # adjoint: 64 uneven d = 3 problems, forward + backward (dB and dT)
+    probs = ti.uneven_batch(64, 32, 192, seed=args.seed)
+    T = [[torch.from_numpy(t).cuda() for t in q["T"]] for q in probs]
+    Bs = [torch.from_numpy(q["B"]).cuda() for q in probs]
+    Gs = [torch.from_numpy(q["G"]).cuda() for q in probs]
+    plan = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs])
+    Xs = [torch.empty_like(b) for b in Bs]
+    msf = _timed(lambda: plan.solve(Bs, Xs), steps, 1)
+    plan.status()
+    msb = _timed(lambda: tt.solve_backward_batched(T, Xs, Gs), steps, 1)
+    out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "forward_flops": plan.flops}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +164,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cores", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -100,9 +205,8 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     tflops = flops / (ms * 1e-3) / 1e12
 
-    # per-kernel-class timing: HIP events around every launch, each on the
-    # stream the launch is on (leaves: the caller's stream; updates: the
-    # plan's side stream)
+    # per-kernel-class timing: a profiling solve with every launch on the
+    # caller's stream and HIP events around each (each kernel's own duration)
     prof = plan.profile(B, X)
     upd, leaf = prof["update"], prof["leaf"]
     ach = upd["flops"] / (upd["ms"] * 1e-3) / 1e12
@@ -114,8 +218,12 @@ def main():
         "leaf_kernel": {"ms": leaf["ms"], "launches": leaf["launches"],
                         "tflops": leaf["flops"] / (leaf["ms"] * 1e-3) / 1e12,
                         "gbs": leaf["bytes"] / (leaf["ms"] * 1e-3) / 1e9},
-        "leaf_span_ms": prof["leaf_span_ms"],
+        "serial_ms": prof["serial_ms"],
     }
+
+    del plan, X
+    torch.cuda.empty_cache()
+    ext = None if args.no_extras else extras(args)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -142,6 +250,7 @@ def main():
         "kernels": kernels,
         "plan_build_s": plan_s,
         "cpu_baseline": cpu,
+        "workloads": ext,
     }
     print(json.dumps(out))
 

@@ -264,9 +264,11 @@ class Plan:
         return X
 
     def profile(self, B, X, stream=None):
-        """Run one solve with timing events around every launch; returns per
-        kernel class ("leaf", "update") the summed launch milliseconds,
-        algorithmic flops, algorithmic HBM bytes and launch count."""
+        """Run one solve with every launch on one stream (each kernel alone)
+        and timing events around every launch; returns per kernel class
+        ("leaf", "update") the summed launch milliseconds, algorithmic flops,
+        algorithmic HBM bytes and launch count, and "serial_ms", the whole
+        serialised solve."""
         out = (ctypes.c_double * 12)()
         _check(lib().tt_plan_profile(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
                                      _stream(stream), out))
@@ -274,7 +276,7 @@ class Plan:
         for k, name in enumerate(["leaf", "update"]):
             res[name] = {"ms": out[4 * k], "flops": out[4 * k + 1], "bytes": out[4 * k + 2],
                          "launches": int(out[4 * k + 3])}
-        res["leaf_span_ms"] = out[8]
+        res["serial_ms"] = out[8]
         return res
 
     def status(self):

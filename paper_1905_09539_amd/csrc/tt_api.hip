@@ -306,12 +306,13 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
                                  P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH, st));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->la[k], st));
         TT_HIP_CHECK(hipEventRecord(P->evL[k], st));
-        if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
-        if (prof) TT_HIP_CHECK(hipEventRecord(prof->ub[k], P->side));
-        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp,
-                                   P->side));
-        if (prof) TT_HIP_CHECK(hipEventRecord(prof->ua[k], P->side));
-        TT_HIP_CHECK(hipEventRecord(P->evU[k], P->side));
+        // profiling runs each kernel alone (updates on the caller's stream)
+        hipStream_t us = prof ? st : P->side;
+        if (k >= 1 && !prof) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
+        if (prof) TT_HIP_CHECK(hipEventRecord(prof->ub[k], us));
+        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp, us));
+        if (prof) TT_HIP_CHECK(hipEventRecord(prof->ua[k], us));
+        TT_HIP_CHECK(hipEventRecord(P->evU[k], us));
     }
     if (W > 0) TT_HIP_CHECK(hipStreamWaitEvent(st, P->evU[W - 1], 0));
     P->last_stream = st;
@@ -790,8 +791,8 @@ int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, doub
         }
         if (W > 0) {
             float ms = 0;
-            TT_HIP_CHECK(hipEventElapsedTime(&ms, pe.lb[0], pe.la[W - 1]));
-            out[8] = ms;  // first leaf start to last leaf end
+            TT_HIP_CHECK(hipEventElapsedTime(&ms, pe.lb[0], pe.ua[W - 1]));
+            out[8] = ms;  // the serialised solve: first leaf start to last update end
         }
     }
     for (auto* v : {&pe.lb, &pe.la, &pe.ub, &pe.ua})

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
         // loaders: A: (row = tid/4, k = 4*(tid%4)..+3); B: (k = tid/16, c = 4*(tid%16)..+3)
         const int la_r = tid >> 2, la_k = (tid & 3) * 4;
         const int lb_k = tid >> 4, lb_c = (tid & 15) * 4;
-        double ra[4], rb[4];
+        double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
         int64_t boff[4];
         bool bval[4];
 #pragma unroll
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
         }
         const bool aval_r = (row0 + la_r) < t.M;
         const double* Arow = T + (int64_t)(t.r0 + row0 + la_r) * nmu + t.k0;
-        auto gload = [&](int kc) {
+        auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 int k = kc + la_k + i;
@@ -240,15 +240,24 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
 #pragma unroll
             for (int i = 0; i < 4; ++i) rb[i] = (kvalid && bval[i]) ? X[boff[i] + roff] : 0.0;
         };
-        gload(0);
-        for (int ch = 0; ch < nchunk; ++ch) {
+        auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 4; ++i) As[(la_k + i) * kLdsRow + la_r] = ra[i];
 #pragma unroll
             for (int i = 0; i < 4; ++i) Bs[lb_k * kLdsRow + lb_c + i] = rb[i];
             __syncthreads();
-            if (ch + 1 < nchunk) gload((ch + 1) * kKC);
+        };
+        // chunk c is computed while chunks c+1 and c+2 are in flight
+        gload(ra0, rb0, 0);
+        if (nchunk > 1) gload(ra1, rb1, kKC);
+        for (int ch = 0; ch < nchunk; ch += 2) {
+            stage(ra0, rb0);
+            if (ch + 2 < nchunk) gload(ra0, rb0, (ch + 2) * kKC);
+            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
+            if (ch + 1 >= nchunk) break;
+            stage(ra1, rb1);
+            if (ch + 3 < nchunk) gload(ra1, rb1, (ch + 3) * kKC);
             mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
         }
 #pragma unroll
@@ -275,8 +284,8 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
         const bool rval = (row0 + lr) < t.M;
         const double* Xrow = X + colOff[lr] + t.k0;
         const double* Trow = T + (int64_t)(t.r0 + row0 + lr) * nmu + t.k0;
-        double ra[4], rb[4];
-        auto gload = [&](int kc) {
+        double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
+        auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 int k = kc + lk4 + i;
@@ -284,8 +293,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                 rb[i] = (rval && k < t.K) ? Trow[k] : 0.0;
             }
         };
-        gload(0);
-        for (int ch = 0; ch < nchunk; ++ch) {
+        auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -293,7 +301,16 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                 Bs[(lk4 + i) * kLdsRow + lr] = rb[i];
             }
             __syncthreads();
-            if (ch + 1 < nchunk) gload((ch + 1) * kKC);
+        };
+        gload(ra0, rb0, 0);
+        if (nchunk > 1) gload(ra1, rb1, kKC);
+        for (int ch = 0; ch < nchunk; ch += 2) {
+            stage(ra0, rb0);
+            if (ch + 2 < nchunk) gload(ra0, rb0, (ch + 2) * kKC);
+            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
+            if (ch + 1 >= nchunk) break;
+            stage(ra1, rb1);
+            if (ch + 3 < nchunk) gload(ra1, rb1, (ch + 3) * kKC);
             mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
         }
 #pragma unroll

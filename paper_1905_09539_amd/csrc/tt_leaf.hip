@@ -306,11 +306,13 @@ __device__ inline bool coupled_solve(double* Xs, double* const (&Ts)[D], const i
 
 }  // namespace
 
-// Three workgroups of four waves share a CU (LDS of a 16^3 leaf is ~50 KB),
-// so the order-3 kernel is held to three waves per SIMD worth of registers;
-// order 4 keeps its 16-unknown tuple solve in registers (one wave per SIMD).
-template <int D>
-__global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 : 3))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
+// NT threads per leaf: 256 for blocks up to 16^3 (three such workgroups share
+// a CU: ~50 KB of LDS each), 64 (one wave, no cross-wave barriers) for blocks
+// up to 10^3, whose hyperplanes hold at most ~75 unknowns.  The order-3
+// kernel is held to three waves per SIMD worth of registers; order 4 keeps
+// its 16-unknown tuple solve in registers (one wave per SIMD).
+template <int D, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 : 3))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
                                                       const ProbDesc* __restrict__ probs,
                                                       const LeafShape* __restrict__ shapes,
                                                       const uint16_t* __restrict__ ents,
@@ -365,7 +367,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
     int32_t* coff = eoff + geom.maxH + 1;                  // coupled-tuple offsets per hyperplane
     int32_t* wsum = coff + geom.maxH + 1;                  // wave totals of the block scan
     const LeafShape sh = shapes[L.shape];
-    for (int i = tid; i <= sh.H; i += kLeafNT) hof[i] = hoffs[sh.hoff + i];
+    for (int i = tid; i <= sh.H; i += NT) hof[i] = hoffs[sh.hoff + i];
 
     double* __restrict__ X = P.X;
     int64_t gbase = 0;
@@ -385,12 +387,12 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
     };
 
     // ---- 1. right-hand side and diagonal blocks
-    for (int base = 0; base < cap; base += kLeafNT * kLoadBatch) {
+    for (int base = 0; base < cap; base += NT * kLoadBatch) {
         double v[kLoadBatch];
         int64_t g[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int e = base + u * kLeafNT + tid;
+            const int e = base + u * NT + tid;
             g[u] = (e < cap) ? gbase + goff(e) : -1;
             v[u] = (g[u] >= 0) ? X[g[u]] : 0.0;
         }
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int e = base + u * kLeafNT + tid;
+            const int e = base + u * NT + tid;
             if (e < cap) Xs[e] = v[u];
         }
     }
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         const double* T = P.T[mu];
         const int64_t n = P.n[mu];
         const float rtp = 1.0f / (float)tp[mu];
-        for (int e = tid; e < sz[mu] * tp[mu]; e += kLeafNT) {
+        for (int e = tid; e < sz[mu] * tp[mu]; e += NT) {
             const int i = qdiv(e, rtp), j = e - i * tp[mu];
             Ts[mu][e] = (j < sz[mu]) ? T[(int64_t)(r0[mu] + i) * n + r0[mu] + j] : 0.0;
         }
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         const double* T = P.T[mu];
         const int64_t n = P.n[mu];
         const int r1 = r0[mu] + sz[mu];
-        for (int e = tid; e < sz[mu] * nxm; e += kLeafNT) {
+        for (int e = tid; e < sz[mu] * nxm; e += NT) {
             const int i = e / nxm, j = e - (e / nxm) * nxm;
             Ta[e] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
         }
@@ -463,7 +465,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         // one thread per fibre along mu
         const int F = cap / sz[mu];
         const int64_t nstep = (int64_t)sz[mu] * gs[mu];  // from row r0+i to row r1+i
-        for (int f = tid; f < F; f += kLeafNT) {
+        for (int f = tid; f < F; f += NT) {
             int eb = 0;
             int64_t gb = gbase;
             {
@@ -531,14 +533,23 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         return ne;
     };
     {
-        const int per = (sh.count + kLeafNT - 1) / kLeafNT;
+        const int per = (sh.count + NT - 1) / NT;
         const int t0 = min(sh.count, tid * per), t1 = min(sh.count, t0 + per);
-        auto entry = [&](int t) -> uint32_t { return ents[sh.ent + t]; };
+        // entries four at a time, so that their global loads overlap
+        auto load4 = [&](int tb, uint32_t (&e4)[4]) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) e4[u] = ents[sh.ent + min(tb + u, t1 - 1)];
+        };
         int cnt = 0;  // elements | coupled tuples << 16
-        for (int t = t0; t < t1; ++t) {
-            int a[D], w[D];
-            const int ne = decode(entry(t), a, w);
-            cnt += ne + ((ne > 1) ? (1 << 16) : 0);
+        for (int tb = t0; tb < t1; tb += 4) {
+            uint32_t e4[4];
+            load4(tb, e4);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int a[D], w[D];
+                const int ne = decode(e4[u], a, w);
+                if (tb + u < t1) cnt += ne + ((ne > 1) ? (1 << 16) : 0);
+            }
         }
         // exclusive block scan: wave scan by shuffles, then wave totals
         const int lane = tid & 63, wv = tid >> 6;
@@ -567,31 +578,39 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
                 coff[h] = oc;
             }
         }
-        for (int t = t0; t < t1; ++t) {
-            if (t == hnext) {  // first tuple of the next hyperplane(s)
-                while (hof[h + 1] <= t) ++h;
-                hnext = hof[h + 1];
-                eoff[h] = on;
-                coff[h] = oc;
-            }
-            const uint32_t e = entry(t);
-            int a[D], w[D];
-            const int ne = decode(e, a, w);
-            for (int q = 0; q < ne; ++q) {
-                // unknown q: the last width-2 mode owns bit 0
-                uint32_t r = 0;
-                int rq = q;
-#pragma unroll
-                for (int mu = D - 1; mu >= 0; --mu) {
-                    const int d = (w[mu] == 2) ? (rq & 1) : 0;
-                    if (w[mu] == 2) rq >>= 1;
-                    r |= (uint32_t)(a[mu] + d) << (kCB * mu);
+        for (int tb = t0; tb < t1; tb += 4) {
+            uint32_t e4[4];
+            load4(tb, e4);
+            for (int u = 0; u < 4 && tb + u < t1; ++u) {
+                const int t = tb + u;
+                if (t == hnext) {  // first tuple of the next hyperplane(s)
+                    while (hof[h + 1] <= t) ++h;
+                    hnext = hof[h + 1];
+                    eoff[h] = on;
+                    coff[h] = oc;
                 }
-                rec[on++] = (uint16_t)r;
+                uint32_t e = e4[0];
+#pragma unroll
+                for (int k = 1; k < 4; ++k)
+                    if (u == k) e = e4[k];
+                int a[D], w[D];
+                const int ne = decode(e, a, w);
+                for (int q = 0; q < ne; ++q) {
+                    // unknown q: the last width-2 mode owns bit 0
+                    uint32_t r = 0;
+                    int rq = q;
+#pragma unroll
+                    for (int mu = D - 1; mu >= 0; --mu) {
+                        const int d = (w[mu] == 2) ? (rq & 1) : 0;
+                        if (w[mu] == 2) rq >>= 1;
+                        r |= (uint32_t)(a[mu] + d) << (kCB * mu);
+                    }
+                    rec[on++] = (uint16_t)r;
+                }
+                if (ne > 1) clist[oc++] = (uint16_t)e;
             }
-            if (ne > 1) clist[oc++] = (uint16_t)e;
         }
-        if (tid == kLeafNT - 1) {
+        if (tid == NT - 1) {
             eoff[sh.H] = on;
             coff[sh.H] = oc;
         }
@@ -605,7 +624,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
     bool ok = true;
     for (int h = 0; h < sh.H; ++h) {
         const int ebeg = eoff[h], eend = eoff[h + 1];
-        for (int i = ebeg + tid; i < eend; i += kLeafNT) {
+        for (int i = ebeg + tid; i < eend; i += NT) {
             const uint32_t r = rec[i];
             int c[D], e = 0;
 #pragma unroll
@@ -636,7 +655,7 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
         const int cbeg = coff[h], cend = coff[h + 1];
         if (cend > cbeg) {  // uniform
             __syncthreads();
-            for (int k = cbeg + tid; k < cend; k += kLeafNT) {
+            for (int k = cbeg + tid; k < cend; k += NT) {
                 int a[D], w[D];
                 decode(clist[k], a, w);
                 int e0 = 0;
@@ -650,10 +669,10 @@ __global__ __launch_bounds__(kLeafNT) __attribute__((amdgpu_waves_per_eu(D == 4 
     if (!ok) atomicOr(status, 1);
 
     // ---- 6. store the solved block
-    for (int base = 0; base < cap; base += kLeafNT * kLoadBatch) {
+    for (int base = 0; base < cap; base += NT * kLoadBatch) {
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int e = base + u * kLeafNT + tid;
+            const int e = base + u * NT + tid;
             if (e < cap) X[gbase + goff(e)] = Xs[e];
         }
     }
@@ -689,20 +708,26 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     if (count <= 0) return hipSuccess;
     const int lds = leaf_lds_bytes(D, bmax, maxtup, maxcpl, maxH);
     const LeafGeom geom = leaf_geometry(D, bmax, maxtup, maxcpl, maxH);
-    dim3 grid((unsigned)count), block(kLeafNT);
+    const bool small = geom.cap <= 1000;
+    dim3 grid((unsigned)count), block(small ? 64 : kLeafNT);
+    const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64> : (const void*)leaf_kernel<3, kLeafNT>)
+                              : (small ? (const void*)leaf_kernel<4, 64> : (const void*)leaf_kernel<4, kLeafNT>);
     if (lds > 64 * 1024) {
-        hipError_t e = (D == 3) ? hipFuncSetAttribute((const void*)leaf_kernel<3>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds)
-                                : hipFuncSetAttribute((const void*)leaf_kernel<4>,
-                                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    if (D == 3)
-        hipLaunchKernelGGL(leaf_kernel<3>, grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs, status,
-                           geom);
+    if (D == 3 && small)
+        hipLaunchKernelGGL((leaf_kernel<3, 64>), grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs,
+                           status, geom);
+    else if (D == 3)
+        hipLaunchKernelGGL((leaf_kernel<3, kLeafNT>), grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs,
+                           status, geom);
+    else if (small)
+        hipLaunchKernelGGL((leaf_kernel<4, 64>), grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs,
+                           status, geom);
     else
-        hipLaunchKernelGGL(leaf_kernel<4>, grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs, status,
-                           geom);
+        hipLaunchKernelGGL((leaf_kernel<4, kLeafNT>), grid, block, lds, st, leaves, first, probs, shapes, ents,
+                           hoffs, status, geom);
     return hipGetLastError();
 }
 
