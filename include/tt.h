@@ -189,14 +189,15 @@ int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream);
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X,
                           void* stream);
 int tt_plan_status(tt_plan plan);
-/* Profiling pass: the same work as tt_plan_solve, every launch on the
- * caller's stream (no overlap of leaf and update kernels, so that each
- * kernel's duration is its own) with HIP timing events around every launch;
- * synchronises.  out[12] receives, for kernel class k (0 = leaf solves,
- * 1 = recursion updates): out[4k] summed launch milliseconds, out[4k+1]
- * algorithmic flops, out[4k+2] algorithmic HBM bytes, out[4k+3] launches;
- * out[8] = milliseconds of the whole serialised solve. */
-int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, double* out);
+/* Profiling pass: the same work as tt_plan_solve with HIP timing events
+ * around every kernel launch, each on the stream the launch is on;
+ * synchronises.  serial != 0 puts every launch on the caller's stream (no
+ * overlap of leaf and update kernels: each duration is the kernel alone).
+ * out[12] receives, for kernel class k (0 = leaf solves, 1 = recursion
+ * updates): out[4k] summed launch milliseconds, out[4k+1] algorithmic flops,
+ * out[4k+2] algorithmic HBM bytes, out[4k+3] launches; out[8] = milliseconds
+ * from the first leaf launch to the end of the last update. */
+int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out);
 double tt_plan_flops(tt_plan plan);
 /* out[4]: [0] refinement iterations of the last solve, [1] its last
  * ||D||_F/||X||_F, [2] plan build seconds (host), [3] host Schur seconds. */

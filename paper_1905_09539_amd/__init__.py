@@ -74,7 +74,7 @@ def lib():
         L.tt_plan_flops.argtypes = [vp]
         L.tt_plan_flops.restype = ctypes.c_double
         L.tt_plan_destroy.argtypes = [vp]
-        L.tt_plan_profile.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
+        L.tt_plan_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.tt_schedule_info.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.tt_plan_create_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, ctypes.POINTER(Opts)]
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
@@ -263,20 +263,21 @@ class Plan:
         _check(lib().tt_plan_solve_batched(self._h, bp, xp, _stream(stream)))
         return X
 
-    def profile(self, B, X, stream=None):
-        """Run one solve with every launch on one stream (each kernel alone)
-        and timing events around every launch; returns per kernel class
-        ("leaf", "update") the summed launch milliseconds, algorithmic flops,
-        algorithmic HBM bytes and launch count, and "serial_ms", the whole
-        serialised solve."""
+    def profile(self, B, X, stream=None, serial=False):
+        """Run one solve with timing events around every launch (on the
+        launch's own stream; serial=True puts every launch on one stream, so
+        each kernel runs alone); returns per kernel class ("leaf", "update")
+        the summed launch milliseconds, algorithmic flops, algorithmic HBM
+        bytes and launch count, and "solve_ms" (first leaf launch to the end
+        of the last update)."""
         out = (ctypes.c_double * 12)()
         _check(lib().tt_plan_profile(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
-                                     _stream(stream), out))
+                                     _stream(stream), int(bool(serial)), out))
         res = {}
         for k, name in enumerate(["leaf", "update"]):
             res[name] = {"ms": out[4 * k], "flops": out[4 * k + 1], "bytes": out[4 * k + 2],
                          "launches": int(out[4 * k + 3])}
-        res["serial_ms"] = out[8]
+        res["solve_ms"] = out[8]
         return res
 
     def status(self):

@@ -291,6 +291,7 @@ int set_pointers(tt_plan_s* P, double* const* X, int count, hipStream_t st) {
 // With prof != NULL, timing events bracket every launch (profiling only).
 struct ProfEvents {
     std::vector<hipEvent_t> lb, la, ub, ua;
+    bool serial = false;  // every launch on the caller's stream
 };
 
 int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int lp = 0) {
@@ -306,9 +307,11 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
                                  P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH, st));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->la[k], st));
         TT_HIP_CHECK(hipEventRecord(P->evL[k], st));
-        // profiling runs each kernel alone (updates on the caller's stream)
-        hipStream_t us = prof ? st : P->side;
-        if (k >= 1 && !prof) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
+        // a serial profiling pass runs each kernel alone (updates on the
+        // caller's stream)
+        const bool serial = prof && prof->serial;
+        hipStream_t us = serial ? st : P->side;
+        if (k >= 1 && !serial) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ub[k], us));
         TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp, us));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ua[k], us));
@@ -752,7 +755,7 @@ int tt_plan_info(tt_plan plan, double* out) {
     return TT_OK;
 }
 
-int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, double* out) {
+int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out) {
     if (!plan || !out) return fail(TT_EINVAL, "NULL argument");
     if (plan->count != 1 || plan->kind != KIND_TRI || plan->prec != TT_FP64)
         return fail(TT_EINVAL, "profile needs a single-problem FP64 triangular plan");
@@ -761,6 +764,7 @@ int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, doub
     plan->last_stream = st;
     const size_t W = plan->sched.waves.size();
     ProfEvents pe;
+    pe.serial = serial != 0;
     for (auto* v : {&pe.lb, &pe.la, &pe.ub, &pe.ua}) {
         v->resize(W);
         for (auto& e : *v) TT_HIP_CHECK(hipEventCreate(&e));
@@ -792,7 +796,7 @@ int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, doub
         if (W > 0) {
             float ms = 0;
             TT_HIP_CHECK(hipEventElapsedTime(&ms, pe.lb[0], pe.ua[W - 1]));
-            out[8] = ms;  // the serialised solve: first leaf start to last update end
+            out[8] = ms;  // first leaf start to last update end
         }
     }
     for (auto* v : {&pe.lb, &pe.la, &pe.ub, &pe.ua})
