@@ -115,45 +115,45 @@ __device__ inline bool tuple_solve4(const double (&Dm)[4][4], double c, double (
 // 8 unknowns: with D_0 = [p q; r t] and K the 4x4 matrix of the other two
 // 2x2 modes (plus c I), the system splits into
 //   (K + pI) x0 + q x1 = b0,   r x0 + (K + tI) x1 = b1,
-// so  [(K + tI)(K + pI) - q r I] x0 = (K + tI) b0 - q b1  and
-//     (K + tI) x1 = b1 - r x0  (K + pI and K + tI commute).
+// so with S = K + tI (the 4-unknown matrix with shift c + t):
+//   [S^2 + (p - t) S - q r I] x0 = S b0 - q b1   (dense 4x4), and
+//   S x1 = b1 - r x0                             (4-unknown tuple solve).
+// S is rebuilt by the second solve, so the elimination holds only Q.
 __device__ inline bool tuple_solve8(const double (&Dm)[4][4], double c, double (&b)[8]) {
-    double Km[4][4];
-    double D2[4][4] = {{Dm[1][0], Dm[1][1], Dm[1][2], Dm[1][3]},
-                       {Dm[2][0], Dm[2][1], Dm[2][2], Dm[2][3]},
-                       {0, 0, 0, 0},
-                       {0, 0, 0, 0}};
-    tuple_matrix<4>(Km, D2, c);
     const double p = Dm[0][0], q = Dm[0][1], r = Dm[0][2], t = Dm[0][3];
-    double S[4][4], Q[4][4], rhs[4];
+    const double D2[4][4] = {{Dm[1][0], Dm[1][1], Dm[1][2], Dm[1][3]},
+                             {Dm[2][0], Dm[2][1], Dm[2][2], Dm[2][3]},
+                             {0, 0, 0, 0},
+                             {0, 0, 0, 0}};
+    double Q[4][4], rhs[4];
+    {
+        double S[4][4];
+        tuple_matrix<4>(S, D2, c + t);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) S[i][j] = Km[i][j] + (i == j ? t : 0.0);
+            for (int j = 0; j < 4; ++j) {
+                double acc = (p - t) * S[i][j] + ((i == j) ? -q * r : 0.0);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+                for (int l = 0; l < 4; ++l) acc = fma(S[i][l], S[l][j], acc);
+                Q[i][j] = acc;
+            }
+            double acc = -q * b[4 + i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            double acc = (i == j) ? -q * r : 0.0;
-#pragma unroll
-            for (int l = 0; l < 4; ++l) acc += S[i][l] * (Km[l][j] + (l == j ? p : 0.0));
-            Q[i][j] = acc;
+            for (int l = 0; l < 4; ++l) acc = fma(S[i][l], b[l], acc);
+            rhs[i] = acc;
         }
-        double acc = -q * b[4 + i];
-#pragma unroll
-        for (int l = 0; l < 4; ++l) acc += S[i][l] * b[l];
-        rhs[i] = acc;
     }
     bool ok = gepp_small<4>(Q, rhs);
-    double rhs1[4];
+    double r4[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         b[i] = rhs[i];
-        rhs1[i] = b[4 + i] - r * rhs[i];
+        r4[i] = b[4 + i] - r * rhs[i];
     }
-    ok = gepp_small<4>(S, rhs1) && ok;
+    ok = tuple_solve4(D2, c + t, r4) && ok;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) b[4 + i] = rhs1[i];
+    for (int i = 0; i < 4; ++i) b[4 + i] = r4[i];
     return ok;
 }
 
@@ -302,6 +302,63 @@ __device__ inline bool coupled_solve(double* Xs, double* const (&Ts)[D], const i
         }
     }
     return ok;
+}
+
+// Explicit inverse of the matrix of a tuple with two or four unknowns (2x2
+// blocks in one or two modes) and the LDS offsets of its unknowns; the
+// matrix depends on T only, so this runs before the unknowns' right-hand
+// sides exist.  With the first 2x2 block D_0 = [p q; r t], K = D_1 + c I and
+// Q = (K + tI)(K + pI) - q r I, the four-unknown matrix [K + pI, qI; rI, K + tI]
+// has the inverse [Q^-1 (K + tI), -q Q^-1; -r Q^-1, (K + pI) Q^-1] (all blocks
+// are polynomials in K, so they commute).
+template <int D>
+__device__ inline bool tuple_inverse(double* const (&Ts)[D], const int (&tp)[D], const int (&ls)[D],
+                                     const int (&a)[D], const int (&w)[D], double (&Mi)[4][4], int (&eq)[4]) {
+    double cdiag = 0.0, p = 0.0, q = 0.0, r = 0.0, t = 0.0, k00 = 0.0, k01 = 0.0, k10 = 0.0, k11 = 0.0;
+    int ne = 1, e0 = 0, s0 = 0, s1 = 0;  // strides of the width-2 modes (bit 1, bit 0 of the unknown index)
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+        const double* Tm = Ts[mu] + a[mu] * tp[mu] + a[mu];
+        e0 += a[mu] * ls[mu];
+        if (w[mu] == 2) {
+            const double d0 = Tm[0], d1 = Tm[1], d2 = Tm[tp[mu]], d3 = Tm[tp[mu] + 1];
+            // the first width-2 mode lands in (p q r t), the second in K
+            if (ne == 1) {
+                p = d0, q = d1, r = d2, t = d3;
+                s1 = ls[mu];
+            } else {
+                k00 = d0, k01 = d1, k10 = d2, k11 = d3;
+                s0 = ls[mu];
+            }
+            ne *= 2;
+        } else {
+            cdiag += Tm[0];
+        }
+    }
+    if (ne == 2) {
+        const double m00 = p + cdiag, m11 = t + cdiag;
+        const double rd = 1.0 / (m00 * m11 - q * r);
+        Mi[0][0] = m11 * rd, Mi[0][1] = -q * rd;
+        Mi[1][0] = -r * rd, Mi[1][1] = m00 * rd;
+        eq[0] = e0, eq[1] = e0 + s1, eq[2] = e0, eq[3] = e0;
+        return isfinite(rd);
+    }
+    k00 += cdiag, k11 += cdiag;
+    // S = K + tI, P = K + pI, Q = S P - q r I
+    const double s00 = k00 + t, s11 = k11 + t, p00 = k00 + p, p11 = k11 + p;
+    const double q00 = s00 * p00 + k01 * k10 - q * r, q01 = s00 * k01 + k01 * p11;
+    const double q10 = k10 * p00 + s11 * k10, q11 = k10 * k01 + s11 * p11 - q * r;
+    const double rd = 1.0 / (q00 * q11 - q01 * q10);
+    const double i00 = q11 * rd, i01 = -q01 * rd, i10 = -q10 * rd, i11 = q00 * rd;  // Q^-1
+    Mi[0][0] = i00 * s00 + i01 * k10, Mi[0][1] = i00 * k01 + i01 * s11;
+    Mi[1][0] = i10 * s00 + i11 * k10, Mi[1][1] = i10 * k01 + i11 * s11;
+    Mi[0][2] = -q * i00, Mi[0][3] = -q * i01, Mi[1][2] = -q * i10, Mi[1][3] = -q * i11;
+    Mi[2][0] = -r * i00, Mi[2][1] = -r * i01, Mi[3][0] = -r * i10, Mi[3][1] = -r * i11;
+    Mi[2][2] = p00 * i00 + k01 * i10, Mi[2][3] = p00 * i01 + k01 * i11;
+    Mi[3][2] = k10 * i00 + p11 * i10, Mi[3][3] = k10 * i01 + p11 * i11;
+    // unknown index: bit 1 -> first width-2 mode, bit 0 -> second
+    eq[0] = e0, eq[1] = e0 + s0, eq[2] = e0 + s1, eq[3] = e0 + s1 + s0;
+    return isfinite(rd);
 }
 
 }  // namespace
@@ -617,13 +674,30 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
     }
     __syncthreads();
 
-    // ---- 5. block back-substitution, one tuple hyperplane per step:
-    // (A) every unknown forms its right-hand side (unknowns of 1x1 tuples
-    // also divide by their eigenvalue sum), (B) coupled tuples solve their
-    // small systems
+    // ---- 5. block back-substitution, one tuple hyperplane per step.
+    // Coupled tuples with up to four unknowns are taken by the highest
+    // threads, which hold no unknowns of the step while its hyperplane has
+    // fewer than NT - (coupled tuples) unknowns: they invert their small
+    // matrix (T only) while the other threads form right-hand sides, and
+    // apply the inverse after the barrier.  (A) every unknown forms its
+    // right-hand side (unknowns of 1x1 tuples also divide by their
+    // eigenvalue sum), (B)
+    // coupled tuples solve their small systems.
     bool ok = true;
     for (int h = 0; h < sh.H; ++h) {
         const int ebeg = eoff[h], eend = eoff[h + 1];
+        const int cbeg = coff[h], cend = coff[h + 1];
+        const int kc = cbeg + (NT - 1 - tid);
+        uint32_t cen = 0;
+        // defined on every path, so nothing of a previous step stays live
+        int pne = 0, peq[4] = {0, 0, 0, 0};
+        double Mi[4][4] = {};
+        if (kc < cend) {
+            int a[D], w[D];
+            cen = clist[kc];
+            pne = decode(cen, a, w);
+            if (pne <= 4 && !tuple_inverse<D>(Ts, tp, ls, a, w, Mi, peq)) ok = false;
+        }
         for (int i = ebeg + tid; i < eend; i += NT) {
             const uint32_t r = rec[i];
             int c[D], e = 0;
@@ -652,10 +726,28 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                 lds[e] = rhs;
             }
         }
-        const int cbeg = coff[h], cend = coff[h + 1];
         if (cend > cbeg) {  // uniform
             __syncthreads();
-            for (int k = cbeg + tid; k < cend; k += NT) {
+            if (pne == 2 || pne == 4) {
+                double rb[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) rb[q] = Xs[peq[q]];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q >= pne) break;
+                    double x = 0.0;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (s < pne) x = fma(Mi[q][s], rb[s], x);
+                    if (!isfinite(x)) ok = false;
+                    Xs[peq[q]] = x;
+                }
+            }
+            // this thread's larger tuple, then tuples beyond one per thread
+            for (int m = 0;; ++m) {
+                const int k = m ? cbeg + m * NT + tid : kc;
+                if (k >= cend) break;
+                if (m == 0 && pne <= 4) continue;
                 int a[D], w[D];
                 decode(clist[k], a, w);
                 int e0 = 0;
