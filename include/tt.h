@@ -198,6 +198,15 @@ int tt_plan_status(tt_plan plan);
  * out[4k+2] algorithmic HBM bytes, out[4k+3] launches; out[8] = milliseconds
  * from the first leaf launch to the end of the last update. */
 int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out);
+/* The same profiled solve, reported per hyperplane wave: waves[6k .. 6k+5]
+ * (k < cap; the plan's wave count is tt_schedule_info's out[3] for its
+ * problem) = start and end of wave k's leaf launch, start and end of the
+ * update launch that runs beside it (milliseconds from the first leaf
+ * launch; -1 when the launch is empty), its leaf blocks and its update
+ * tiles.  waves is host memory of at least 6 cap doubles, owned by the
+ * caller.  Same plan restrictions and errors as tt_plan_profile. */
+int tt_plan_profile_waves(tt_plan plan, const double* B, double* X, void* stream, int serial, double* waves,
+                          int64_t cap);
 double tt_plan_flops(tt_plan plan);
 /* out[4]: [0] refinement iterations of the last solve, [1] its last
  * ||D||_F/||X||_F, [2] plan build seconds (host), [3] host Schur seconds. */

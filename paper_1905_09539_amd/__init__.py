@@ -43,7 +43,7 @@ SYMBOLS = [
     "solve_general_tensor", "solve_backward", "solve_tri_tensor_batched",
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
-    "tt_schedule_info", "tt_plan_profile", "tt_plan_create_general", "tt_plan_info", "tt_schur_host",
+    "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host",
 ]
 
 
@@ -278,6 +278,22 @@ class Plan:
             res[name] = {"ms": out[4 * k], "flops": out[4 * k + 1], "bytes": out[4 * k + 2],
                          "launches": int(out[4 * k + 3])}
         res["solve_ms"] = out[8]
+        return res
+
+    def profile_waves(self, B, X, waves, stream=None, serial=False):
+        """Per-wave timeline of one profiled solve: a list with, for each of
+        the plan's `waves` hyperplane waves, a dict of the leaf launch's and
+        the update launch's start/end (ms from the first leaf launch, None
+        for an empty launch), its leaf blocks and its update tiles."""
+        out = (ctypes.c_double * (6 * waves))()
+        _check(lib().tt_plan_profile_waves(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
+                                           _stream(stream), int(bool(serial)), out, ctypes.c_int64(waves)))
+        res = []
+        for k in range(waves):
+            o = out[6 * k:6 * k + 6]
+            res.append({"leaf": None if o[0] < 0 else (o[0], o[1]),
+                        "update": None if o[2] < 0 else (o[2], o[3]),
+                        "leaves": int(o[4]), "tiles": int(o[5])})
         return res
 
     def status(self):

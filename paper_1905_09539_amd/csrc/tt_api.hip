@@ -755,8 +755,13 @@ int tt_plan_info(tt_plan plan, double* out) {
     return TT_OK;
 }
 
-int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out) {
-    if (!plan || !out) return fail(TT_EINVAL, "NULL argument");
+// One profiled solve; fills the per-class totals of tt_plan_profile into out
+// (when not NULL) and, per wave, six numbers into waves (when not NULL):
+// leaf launch start and end, update launch start and end (milliseconds from
+// the first leaf launch; -1 for an empty launch), leaf blocks and update tiles.
+static int profile_run(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out,
+                       double* waves, int64_t cap) {
+    if (!plan) return fail(TT_EINVAL, "NULL argument");
     if (plan->count != 1 || plan->kind != KIND_TRI || plan->prec != TT_FP64)
         return fail(TT_EINVAL, "profile needs a single-problem FP64 triangular plan");
     hipStream_t st = (hipStream_t)stream;
@@ -798,10 +803,42 @@ int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int 
             TT_HIP_CHECK(hipEventElapsedTime(&ms, pe.lb[0], pe.ua[W - 1]));
             out[8] = ms;  // first leaf start to last update end
         }
+        if (waves) {
+            for (size_t k = 0; k < W && (int64_t)k < cap; ++k) {
+                const Wave& wv = plan->sched.waves[k];
+                double* o = waves + 6 * k;
+                float a = 0, b = 0;
+                o[0] = o[1] = o[2] = o[3] = -1.0;
+                if (wv.leaf_count > 0) {
+                    TT_HIP_CHECK(hipEventElapsedTime(&a, pe.lb[0], pe.lb[k]));
+                    TT_HIP_CHECK(hipEventElapsedTime(&b, pe.lb[0], pe.la[k]));
+                    o[0] = a, o[1] = b;
+                }
+                if (wv.item_count > 0) {
+                    TT_HIP_CHECK(hipEventElapsedTime(&a, pe.lb[0], pe.ub[k]));
+                    TT_HIP_CHECK(hipEventElapsedTime(&b, pe.lb[0], pe.ua[k]));
+                    o[2] = a, o[3] = b;
+                }
+                o[4] = (double)wv.leaf_count;
+                o[5] = (double)wv.item_count;
+            }
+        }
     }
     for (auto* v : {&pe.lb, &pe.la, &pe.ub, &pe.ua})
         for (auto& e : *v) (void)hipEventDestroy(e);
     return rc;
+}
+
+int tt_plan_profile(tt_plan plan, const double* B, double* X, void* stream, int serial, double* out) {
+    if (!out) return fail(TT_EINVAL, "NULL argument");
+    return profile_run(plan, B, X, stream, serial, out, nullptr, 0);
+}
+
+int tt_plan_profile_waves(tt_plan plan, const double* B, double* X, void* stream, int serial, double* waves,
+                          int64_t cap) {
+    if (!waves || cap < 0) return fail(TT_EINVAL, "NULL argument or negative capacity");
+    double tot[12];
+    return profile_run(plan, B, X, stream, serial, tot, waves, cap);
 }
 
 int tt_plan_status(tt_plan plan) {

@@ -386,6 +386,12 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             }
         }
         wv.item_count = (int64_t)s.items.size() - wv.item_first;
+        // longest tiles first (the work of a tile grows with K), so that the
+        // launch does not end on a few long tiles; tiles of one task stay
+        // adjacent
+        std::stable_sort(s.items.begin() + wv.item_first, s.items.end(), [&](const WorkItem& a, const WorkItem& b) {
+            return s.tasks[(size_t)a.task].K > s.tasks[(size_t)b.task].K;
+        });
         s.waves.push_back(wv);
     }
     if (!triggered[(size_t)(W > 0 ? W - 1 : 0)].empty()) {

@@ -268,3 +268,38 @@ def test_mixed_precision_first_correction_is_fp32_sized():
     assert info["iterations"] == 1
     assert 1e-11 < info["ratio"] < 1e-4
     assert rel(host(X), oracle.lap_solve(p["T"], p["B"])) <= 1e-9
+
+
+# ---------------------------------------------------------------- per-wave profile
+def test_profile_waves_timeline():
+    """The per-wave profile runs the same solve (identical X) and its wave
+    table adds up to the host schedule: every leaf block and update tile once,
+    launch intervals ordered, each wave's leaf after the previous wave's."""
+    n = 96
+    p = ti.laplace_tri((n, n, n), seed=7, bumps="every8")
+    info = tt().schedule_info(p["T"], (n, n, n), nmin=16)
+    T = [dev(t) for t in p["T"]]
+    B = dev(p["B"])
+    X0 = torch.empty_like(B)
+    X1 = torch.empty_like(B)
+    plan = tt().Plan(T, B.shape, nmin=16)
+    plan.solve(B, X0)
+    W = int(info["waves"])
+    print("case profile_waves", n, W, flush=True)
+    waves = plan.profile_waves(B, X1, W)
+    plan.status()
+    assert np.array_equal(host(X0), host(X1))
+    assert sum(w["leaves"] for w in waves) == int(info["leaves"])
+    assert sum(w["tiles"] for w in waves) == int(info["items"])
+    prev_leaf_end = 0.0
+    for k, w in enumerate(waves):
+        assert (w["leaf"] is None) == (w["leaves"] == 0)
+        assert (w["update"] is None) == (w["tiles"] == 0)
+        if w["leaf"] is not None:
+            assert w["leaf"][0] <= w["leaf"][1]
+            assert w["leaf"][0] >= prev_leaf_end - 1e-3
+            prev_leaf_end = w["leaf"][1]
+        if w["update"] is not None:
+            assert w["update"][0] <= w["update"][1]
+    assert waves[0]["leaf"][0] == 0.0
+    plan.close()
