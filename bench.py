@@ -103,6 +103,20 @@ def _residual(A, X, B):
     return float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
 
 
+def _pair_residual(A, C, X, B):
+    """||B - sum_mu X x_1 C_1 .. x_mu A_mu .. x_d C_d||_F / ||B||_F (torch)."""
+    import torch
+    R = B.clone()
+    d = X.dim()
+    for mu in range(d):
+        Y = X
+        for nu in range(d):
+            M = A[nu] if nu == mu else C[nu]
+            Y = torch.movedim(torch.tensordot(M, Y, dims=([1], [nu])), 0, nu)
+        R -= Y
+    return float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
+
+
 def extras(args):
     """The other workloads of the method, timed the same way (inputs resident
     in HBM, HIP events on the caller's stream)."""
@@ -166,6 +180,22 @@ def extras(args):
                                                          "tflops": plan.flops / (ms * 1e-3) / 1e12}
         del plan, A, C, B, X, p
         torch.cuda.empty_cache()
+
+    # dense pairs, d = 4 (96, 96, 96, 96): host QZ per mode, then transforms
+    # and the triangular solve on the GPU
+    p = ti.pair_dense((96, 96, 96, 96), seed=args.seed)
+    B = torch.from_numpy(p["B"]).cuda()
+    X = torch.empty_like(B)
+    plan = tt.Plan(p["A"], B.shape, C=p["C"], general=True)
+    ms = _timed(lambda: plan.solve(B, X), steps, 1)
+    plan.status()
+    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+    Cd = [torch.from_numpy(c).cuda() for c in p["C"]]
+    out["general_pair_96x96x96x96"] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
+                                       "host_qz_s": plan.info()["schur_seconds"],
+                                       "residual": _pair_residual(Ad, Cd, X, B)}
+    del plan, Ad, Cd, B, X, p
+    torch.cuda.empty_cache()
 
     # adjoint: 64 uneven d = 3 problems, forward + backward (dB and dT)
     probs = ti.uneven_batch(64, 32, 192, seed=args.seed)

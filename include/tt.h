@@ -182,6 +182,19 @@ int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T
  * TT_MP_FP32).  A_host: HOST pointers to row-major n[mu] x n[mu] matrices. */
 int tt_plan_create_general(tt_plan* out, int d, const int64_t* n,
                            const double* const* A_host, const tt_opts* opts);
+
+/* Dense pairs: plan for  sum_mu X x_1 C_1 .. x_mu A_mu .. x_d C_d = B  with
+ * general dense HOST coefficients A_host[mu], C_host[mu] (row-major n_mu x
+ * n_mu, C_mu nonsingular), the pencil form of Sec. 3: host QZ per mode
+ * (A = Q S Z^T, C = Q T Z^T, Algorithm 4's reduction), then on the GPU
+ * B~ = B x_mu (T_mu^{-1} Q_mu^T), the triangular solve with T_mu^{-1} S_mu
+ * (upper quasi-triangular) and X = X~ x_mu Z_mu.  Solve with tt_plan_solve
+ * (B and X device row-major tensors of the plan's shape).  FP64 only.
+ * Errors: TT_EINVAL (bad arguments, non-finite entries, mixed precision
+ * requested, no QZ convergence), TT_ESINGULAR (some C_mu singular to working
+ * precision), TT_ENOMEM. */
+int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
+                                const double* const* C_host, const tt_opts* opts);
 int tt_plan_create_batched(tt_plan* out, int count, const int* d,
                            const int64_t* const* n, const double* const* const* T,
                            int trans, const tt_opts* opts);
@@ -228,6 +241,16 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
  * HOST row-major n x n arrays (A is not modified).  No GPU is used.
  * Errors: TT_EINVAL (bad arguments, non-finite entries, no convergence). */
 int tt_schur_host(int n, const double* A, double* T, double* U);
+
+/* Host-only real generalized Schur (QZ) decomposition of the pencil (A, C),
+ * the host step of Algorithm 4 (Sec. 3): A = Q S Z^T, C = Q T Z^T with S
+ * upper quasi-triangular (2x2 diagonal blocks only for complex eigenvalue
+ * pairs), T upper triangular, Q and Z orthogonal (Householder QR of C, Givens
+ * Hessenberg-triangular reduction, implicit double-shift QZ iteration).
+ * A, C, S, T, Q, Z: HOST row-major n x n arrays (A and C are not modified).
+ * No GPU is used.  Errors: TT_EINVAL (bad arguments, non-finite entries, no
+ * convergence), TT_ESINGULAR (C singular to working precision). */
+int tt_qz_host(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z);
 
 #ifdef __cplusplus
 }

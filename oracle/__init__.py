@@ -195,6 +195,19 @@ def dense_solve_with_factors(Q, T, B, precision="f64"):
     return Xt
 
 
+def pair_dense_solve_with_factors(Q, S, T, Z, B, precision="f64"):
+    """X for the dense pair form with known generalized Schur factors
+    A_mu = Q_mu S_mu Z_mu^T, C_mu = Q_mu T_mu Z_mu^T (Sec. 3):
+    B~ = B x_mu Q_mu^T, X~ = pair_solve(S, T, B~), X = X~ x_mu Z_mu."""
+    W = _f64(B)
+    for mu, q in enumerate(Q):
+        W = mode_product(W, _f64(q).T.copy(), mu, precision)
+    Xt = pair_solve(S, T, W, method="reduced", precision=precision)
+    for mu, z in enumerate(Z):
+        Xt = mode_product(Xt, _f64(z), mu, precision)
+    return Xt
+
+
 def num_threads():
     return lib().oracle_num_threads()
 

@@ -43,7 +43,8 @@ SYMBOLS = [
     "solve_general_tensor", "solve_backward", "solve_tri_tensor_batched",
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
-    "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host",
+    "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
+    "tt_plan_create_general_pair",
 ]
 
 
@@ -79,6 +80,11 @@ def lib():
         L.tt_plan_create_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, ctypes.POINTER(Opts)]
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.tt_schur_host.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.tt_qz_host.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.tt_plan_create_general_pair.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp,
+                                                  ctypes.POINTER(Opts)]
+        L.tt_plan_profile_waves.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -205,16 +211,37 @@ def schur_host(A):
     return T, U
 
 
+def qz_host(A, C):
+    """Host real generalized Schur decomposition A = Q S Z^T, C = Q T Z^T
+    (numpy in, numpy out: S, T, Q, Z)."""
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    C = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    n = A.shape[0]
+    S, T, Q, Z = (np.zeros_like(A) for _ in range(4))
+    _check(lib().tt_qz_host(n, A.ctypes.data, C.ctypes.data, S.ctypes.data, T.ctypes.data, Q.ctypes.data,
+                            Z.ctypes.data))
+    return S, T, Q, Z
+
+
 class Plan:
     """A reusable schedule for solving with fixed coefficients (tt_plan_*).
     T: device coefficient list (C: optional device list for the pair form);
-    general=True takes T as HOST dense matrices (Algorithm 1 pipeline)."""
+    general=True takes T (and C, for the pair form) as HOST dense matrices
+    (Algorithm 1 pipeline; with C: host QZ, Sec. 3)."""
 
     def __init__(self, T, shape=None, nmin=0, trans=False, batch_T=None, batch_shapes=None, C=None,
                  general=False, prec=TT_FP64, tol=1e-13, max_iter=10):
         self._h = ctypes.c_void_p()
         o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter)
-        if general:
+        if general and C is not None:
+            mats, ap = _host_mats(T)
+            cmats, cp = _host_mats(C)
+            self._keep = [mats, ap, cmats, cp]
+            self.count = 1
+            self.shapes = [tuple(int(x) for x in shape)]
+            _check(lib().tt_plan_create_general_pair(ctypes.byref(self._h), len(shape), _shape(shape), ap, cp,
+                                                     ctypes.byref(o)))
+        elif general:
             mats, ap = _host_mats(T)
             self._keep = [mats, ap]
             self.count = 1

@@ -1,6 +1,7 @@
 // C ABI of the solver (declared in include/tt.h): argument validation, plan
 // construction (host) and the ordered launch sequence on one HIP stream.
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -727,6 +728,78 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n, const double* 
     return TT_OK;
 }
 
+// Dense pairs (A_mu, C_mu): per mode the QZ decomposition A = Q S Z^T,
+// C = Q T Z^T turns the equation into the triangular pair (S_mu, T_mu) for
+// X~ = X x_mu Z_mu^T (all modes) with right-hand side B x_mu Q_mu^T, and the
+// pair reduction of the triangular pair form into the Laplace-like equation
+// with T_mu^{-1} S_mu and right-hand side B x_mu (T_mu^{-1} Q_mu^T).  So the
+// GPU runs the dense pipeline with pre-transforms T_mu^{-1} Q_mu^T and
+// post-transforms Z_mu.
+int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
+                                const double* const* C_host, const tt_opts* opts) {
+    if (!out) return fail(TT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A_host || !C_host) return fail(TT_EINVAL, "coefficient array is NULL");
+    if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "mixed precision is not supported for the pair form");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    HostProblem probe;
+    int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
+    if (rc) return rc;
+    std::vector<std::vector<double>> S((size_t)d), T((size_t)d), Q((size_t)d), Z((size_t)d), Tinv;
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] > 16384) return fail(TT_EINVAL, "mode size too large for the host QZ decomposition");
+        if ((!A_host[mu] || !C_host[mu]) && n[mu] > 0) return fail(TT_EINVAL, "coefficient pointer is NULL");
+        const size_t nn = (size_t)(n[mu] * n[mu]);
+        for (auto* v : {&S, &T, &Q, &Z}) (*v)[(size_t)mu].assign(nn, 0.0);
+    }
+    {
+        std::vector<int> rcs((size_t)d, TT_OK);
+        std::vector<std::string> msg((size_t)d);
+        std::vector<std::thread> th;
+        for (int mu = 0; mu < d; ++mu)
+            th.emplace_back([&, mu] {
+                rcs[(size_t)mu] = qz_real((int)n[mu], A_host[mu], C_host[mu], S[(size_t)mu].data(),
+                                          T[(size_t)mu].data(), Q[(size_t)mu].data(), Z[(size_t)mu].data(),
+                                          msg[(size_t)mu]);
+            });
+        for (auto& t : th) t.join();
+        for (int mu = 0; mu < d; ++mu)
+            if (rcs[(size_t)mu]) return fail(rcs[(size_t)mu], "mode " + std::to_string(mu) + ": " + msg[(size_t)mu]);
+    }
+    P->schur_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if ((rc = pair_reduce(d, n, S, T, Tinv))) return rc;  // S <- T^{-1} S
+    std::vector<std::vector<double>> pre((size_t)d);
+    for (int mu = 0; mu < d; ++mu) {  // pre = T^{-1} Q^T (T^{-1} upper triangular)
+        const int64_t m = n[mu];
+        const std::vector<double>& ti = Tinv[(size_t)mu];
+        const std::vector<double>& q = Q[(size_t)mu];
+        std::vector<double>& pm = pre[(size_t)mu];
+        pm.assign((size_t)(m * m), 0.0);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t k = i; k < m; ++k) {
+                const double f = ti[(size_t)(i * m + k)];
+                if (f == 0.0) continue;
+                for (int64_t j = 0; j < m; ++j) pm[(size_t)(i * m + j)] += f * q[(size_t)(j * m + k)];
+            }
+    }
+    if ((rc = plan_begin(P.get(), d, n, S, 0))) return rc;
+    P->kind = KIND_GENERAL;
+    if ((rc = finish_plan(P.get(), opts ? opts->nmin : 0))) return rc;
+    const HostProblem& hp = P->sched.probs[0];
+    P->pre.assign((size_t)d, nullptr);
+    P->post.assign((size_t)d, nullptr);
+    for (int mu = 0; mu < d; ++mu) {
+        if ((rc = upload_matrix(P.get(), pre[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
+        if ((rc = upload_matrix(P.get(), Z[(size_t)mu], &P->post[(size_t)mu]))) return rc;
+    }
+    if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
+    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 2);
+    P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P.release();
+    return TT_OK;
+}
+
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X, void* stream) {
     if (!plan || !B || !X) return fail(TT_EINVAL, "NULL argument");
     hipStream_t st = (hipStream_t)stream;
@@ -982,6 +1055,14 @@ int tt_schur_host(int n, const double* A, double* T, double* U) {
     if (n < 0 || (n > 0 && (!A || !T || !U))) return fail(TT_EINVAL, "bad arguments");
     std::string err;
     int rc = schur_real(n, A, T, U, err);
+    if (rc) return fail(rc, err);
+    return TT_OK;
+}
+
+int tt_qz_host(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z) {
+    if (n < 0 || (n > 0 && (!A || !C || !S || !T || !Q || !Z))) return fail(TT_EINVAL, "bad arguments");
+    std::string err;
+    int rc = qz_real(n, A, C, S, T, Q, Z, err);
     if (rc) return fail(rc, err);
     return TT_OK;
 }

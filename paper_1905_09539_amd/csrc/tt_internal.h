@@ -169,6 +169,8 @@ hipError_t launch_f64_to_f32(const double* x, float* y, int64_t n, hipStream_t s
 hipError_t launch_f32_to_f64(const float* x, double* y, int64_t n, hipStream_t st);
 
 // Host real Schur decomposition A = U T U^T (tt_schur.cpp), row-major.
+int qz_real(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z,
+            std::string& err);
 int schur_real(int n, const double* A, double* T, double* U, std::string& err);
 int schur_real_many(int count, const int* n, const double* const* A, double* const* T, double* const* U,
                     std::string& err);

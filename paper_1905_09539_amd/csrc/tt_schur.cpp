@@ -221,11 +221,282 @@ int schur_one(int n, const double* A, double* Tout, double* Uout, std::string& e
     return TT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Real generalized Schur (QZ) decomposition of a pencil (A, C), the host step
+// of Algorithm 4 (Sec. 3): A = Q S Z^T, C = Q T Z^T with S upper
+// quasi-triangular, T upper triangular, Q and Z orthogonal.  Method
+// (Golub & Van Loan, Sec. 7.7; Moler & Stewart): QR of C, Givens reduction
+// to Hessenberg-triangular form, the implicit double-shift QZ iteration with
+// deflation on the full matrices, and every converged 2x2 block with real
+// eigenvalues split into two 1x1 blocks.  C must be nonsingular (a tiny
+// diagonal entry of T, i.e. an infinite eigenvalue, is reported).
+
+// rows i1, i2 of M, columns c0..c1-1:  (x, y) <- (c x + s y, -s x + c y)
+void rot_rows(Mat& M, int i1, int i2, double c, double s, int c0, int c1) {
+    for (int j = c0; j < c1; ++j) {
+        const double x = M(i1, j), y = M(i2, j);
+        M(i1, j) = c * x + s * y;
+        M(i2, j) = -s * x + c * y;
+    }
+}
+
+// columns j1, j2 of M, rows r0..r1-1:  (x, y) <- (c x - s y, s x + c y)
+void rot_cols(Mat& M, int j1, int j2, double c, double s, int r0, int r1) {
+    for (int i = r0; i < r1; ++i) {
+        const double x = M(i, j1), y = M(i, j2);
+        M(i, j1) = c * x - s * y;
+        M(i, j2) = s * x + c * y;
+    }
+}
+
+// Right reflector (I - beta w w^T) of length m with x^T (I - beta w w^T) =
+// alpha e_m^T (x = the m entries of a row): the left reflector of the
+// reversed row, reversed.
+double householder_last(const double* x, int m, double* w) {
+    double xr[3], vr[3];
+    for (int i = 0; i < m; ++i) xr[i] = x[m - 1 - i];
+    const double beta = householder(xr, m, vr);
+    for (int i = 0; i < m; ++i) w[i] = vr[m - 1 - i];
+    return beta;
+}
+
+int qz_one(int n, const double* A, const double* C, double* Sout, double* Tout, double* Qout, double* Zout,
+           std::string& err) {
+    Mat H(n), R(n), Q(n), Z(n);
+    std::memcpy(H.a.data(), A, sizeof(double) * (size_t)n * n);
+    std::memcpy(R.a.data(), C, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) Q(i, i) = Z(i, i) = 1.0;
+    for (size_t i = 0; i < H.a.size(); ++i)
+        if (!std::isfinite(H.a[i]) || !std::isfinite(R.a[i])) {
+            err = "coefficient matrix has a non-finite entry";
+            return TT_EINVAL;
+        }
+    std::vector<double> x((size_t)n + 3), v((size_t)n + 3);
+    // 1. C = Q_1 R
+    for (int k = 0; k + 1 < n; ++k) {
+        const int m = n - k;
+        for (int i = 0; i < m; ++i) x[i] = R(k + i, k);
+        const double beta = householder(x.data(), m, v.data());
+        apply_left(R, k, m, k, n, v.data(), beta);
+        apply_left(H, k, m, 0, n, v.data(), beta);
+        apply_right(Q, k, m, 0, n, v.data(), beta);
+        for (int i = k + 1; i < n; ++i) R(i, k) = 0.0;
+    }
+    // 2. Hessenberg-triangular form: zero H below the subdiagonal column by
+    // column (left rotations), each fill-in of R removed by a right rotation
+    for (int j = 0; j + 2 < n; ++j)
+        for (int i = n - 1; i >= j + 2; --i) {
+            double a = H(i - 1, j), b = H(i, j);
+            if (b != 0.0) {
+                const double r = std::hypot(a, b), c = a / r, s = b / r;
+                rot_rows(H, i - 1, i, c, s, j, n);
+                rot_rows(R, i - 1, i, c, s, i - 1, n);
+                rot_cols(Q, i - 1, i, c, -s, 0, n);  // Q <- Q G^T
+                H(i, j) = 0.0;
+            }
+            a = R(i, i - 1);
+            b = R(i, i);
+            if (a != 0.0) {
+                const double r = std::hypot(a, b), c = b / r, s = a / r;
+                rot_cols(R, i - 1, i, c, s, 0, i + 1);
+                rot_cols(H, i - 1, i, c, s, 0, n);
+                rot_cols(Z, i - 1, i, c, s, 0, n);
+                R(i, i - 1) = 0.0;
+            }
+        }
+    // 3. double-shift QZ with deflation
+    const double eps = std::ldexp(1.0, -52);
+    double anorm = 0.0, bnorm = 0.0;
+    for (size_t i = 0; i < H.a.size(); ++i) {
+        anorm = std::fmax(anorm, std::fabs(H.a[i]));
+        bnorm = std::fmax(bnorm, std::fabs(R.a[i]));
+    }
+    if (bnorm == 0.0) {
+        err = "C is zero";
+        return TT_ESINGULAR;
+    }
+    auto singular = [&](int lo, int hi) {
+        for (int k = lo; k <= hi; ++k)
+            if (std::fabs(R(k, k)) <= eps * bnorm) return true;
+        return false;
+    };
+    int p = n - 1, iter = 0, total = 0;
+    while (p >= 1) {
+        int l = p;
+        while (l >= 1) {
+            double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
+            if (s == 0.0) s = anorm;
+            if (std::fabs(H(l, l - 1)) <= eps * s) {
+                H(l, l - 1) = 0.0;
+                break;
+            }
+            --l;
+        }
+        if (singular(l, p)) {
+            err = "C is singular to working precision (infinite generalized eigenvalue)";
+            return TT_ESINGULAR;
+        }
+        if (l == p) {  // 1x1 block converged
+            --p;
+            iter = 0;
+            continue;
+        }
+        if (l == p - 1) {  // 2x2 block converged: split it when its eigenvalues are real
+            const int k = p - 1;
+            const double h00 = H(k, k), h01 = H(k, k + 1), h10 = H(k + 1, k), h11 = H(k + 1, k + 1);
+            const double r00 = R(k, k), r01 = R(k, k + 1), r11 = R(k + 1, k + 1);
+            // det(H2 - lam R2) = qa lam^2 + qb lam + qc
+            const double qa = r00 * r11, qb = -(h00 * r11 + h11 * r00 - h10 * r01), qc = h00 * h11 - h01 * h10;
+            const double disc = qb * qb - 4.0 * qa * qc;
+            if (disc >= 0.0) {
+                const double sq = std::sqrt(disc);
+                const double q = -0.5 * (qb + (qb >= 0.0 ? sq : -sq));
+                const double lam = (std::fabs(q) > 0.0 && std::fabs(qa) > 0.0) ? q / qa : qc / q;
+                // right eigenvector z: (H2 - lam R2) z = 0 from the larger row
+                const double m00 = h00 - lam * r00, m01 = h01 - lam * r01, m10 = h10, m11 = h11 - lam * r11;
+                double z0 = m01, z1 = -m00;
+                if (std::hypot(m10, m11) > std::hypot(m00, m01)) {
+                    z0 = m11;
+                    z1 = -m10;
+                }
+                const double zr = std::hypot(z0, z1);
+                if (zr > 0.0) {
+                    // columns (k, k+1) <- first column z / |z|
+                    const double c = z0 / zr, s = z1 / zr;
+                    rot_cols(H, k, k + 1, c, -s, 0, k + 2);
+                    rot_cols(R, k, k + 1, c, -s, 0, k + 2);
+                    rot_cols(Z, k, k + 1, c, -s, 0, n);
+                    // rows (k, k+1): zero R(k+1, k) (H(k+1, k) follows)
+                    const double a = R(k, k), b = R(k + 1, k);
+                    const double r = std::hypot(a, b);
+                    if (r > 0.0) {
+                        const double cc = a / r, ss = b / r;
+                        rot_rows(H, k, k + 1, cc, ss, k, n);
+                        rot_rows(R, k, k + 1, cc, ss, k, n);
+                        rot_cols(Q, k, k + 1, cc, -ss, 0, n);
+                    }
+                    H(k + 1, k) = 0.0;
+                    R(k + 1, k) = 0.0;
+                }
+            }
+            p -= 2;
+            iter = 0;
+            continue;
+        }
+        if (++total > 40 * n) {
+            err = "QZ iteration did not converge";
+            return TT_EINVAL;
+        }
+        ++iter;
+        // shifts: eigenvalues of the trailing 2x2 block of M = H R^-1
+        double s, t;
+        {
+            const double r00 = R(p - 2, p - 2), r01 = R(p - 2, p - 1), r02 = R(p - 2, p);
+            const double r11 = R(p - 1, p - 1), r12 = R(p - 1, p), r22 = R(p, p);
+            const double i11 = 1.0 / r11, i22 = 1.0 / r22;
+            const double i01 = -r01 * i11 / r00, i12 = -r12 * i22 / r11;
+            const double i02 = -(r01 * i12 + r02 * i22) / r00;
+            const double ma = H(p - 1, p - 2) * i01 + H(p - 1, p - 1) * i11;
+            const double mb = H(p - 1, p - 2) * i02 + H(p - 1, p - 1) * i12 + H(p - 1, p) * i22;
+            const double mc = H(p, p - 1) * i11;
+            const double md = H(p, p - 1) * i12 + H(p, p) * i22;
+            if (iter % 11 == 10) {  // exceptional shift
+                const double w = std::fabs(mc) + std::fabs(H(p - 1, p - 2) * i11);
+                const double z = md + 0.75 * w;
+                s = 2.0 * z;
+                t = z * z;
+            } else {
+                s = ma + md;
+                t = ma * md - mb * mc;
+            }
+        }
+        // first column of (M - a1 I)(M - a2 I) at the window start
+        double xx, yy, zz;
+        {
+            const double u0 = H(l, l) / R(l, l), u1 = H(l + 1, l) / R(l, l);
+            const double w1 = u1 / R(l + 1, l + 1);
+            const double w0 = (u0 - R(l, l + 1) * w1) / R(l, l);
+            xx = H(l, l) * w0 + H(l, l + 1) * w1 - s * u0 + t;
+            yy = H(l + 1, l) * w0 + H(l + 1, l + 1) * w1 - s * u1;
+            zz = H(l + 2, l + 1) * w1;
+        }
+        for (int k = l; k <= p - 2; ++k) {
+            double xv[3] = {xx, yy, zz}, vv[3];
+            double beta = householder(xv, 3, vv);
+            const int q = (k > l) ? k - 1 : l;
+            apply_left(H, k, 3, q, n, vv, beta);
+            apply_left(R, k, 3, k, n, vv, beta);
+            apply_right(Q, k, 3, 0, n, vv, beta);
+            if (k > l) {
+                H(k + 1, k - 1) = 0.0;
+                H(k + 2, k - 1) = 0.0;
+            }
+            const int rh = (k + 4 < p + 1) ? k + 4 : p + 1;  // rows of H touched by the bulge
+            // restore R: zero R(k+2, k), R(k+2, k+1), then R(k+1, k)
+            double rv[3] = {R(k + 2, k), R(k + 2, k + 1), R(k + 2, k + 2)}, w[3];
+            beta = householder_last(rv, 3, w);
+            apply_right(R, k, 3, 0, k + 3, w, beta);
+            apply_right(H, k, 3, 0, rh, w, beta);
+            apply_right(Z, k, 3, 0, n, w, beta);
+            R(k + 2, k) = 0.0;
+            R(k + 2, k + 1) = 0.0;
+            double rv2[2] = {R(k + 1, k), R(k + 1, k + 1)}, w2[2];
+            beta = householder_last(rv2, 2, w2);
+            apply_right(R, k, 2, 0, k + 2, w2, beta);
+            apply_right(H, k, 2, 0, rh, w2, beta);
+            apply_right(Z, k, 2, 0, n, w2, beta);
+            R(k + 1, k) = 0.0;
+            xx = H(k + 1, k);
+            yy = H(k + 2, k);
+            if (k < p - 2) zz = H(k + 3, k);
+        }
+        {
+            double xv[2] = {xx, yy}, vv[2];
+            double beta = householder(xv, 2, vv);
+            apply_left(H, p - 1, 2, p - 2, n, vv, beta);
+            apply_left(R, p - 1, 2, p - 1, n, vv, beta);
+            apply_right(Q, p - 1, 2, 0, n, vv, beta);
+            H(p, p - 2) = 0.0;
+            double rv2[2] = {R(p, p - 1), R(p, p)}, w2[2];
+            beta = householder_last(rv2, 2, w2);
+            apply_right(R, p - 1, 2, 0, p + 1, w2, beta);
+            apply_right(H, p - 1, 2, 0, p + 1, w2, beta);
+            apply_right(Z, p - 1, 2, 0, n, w2, beta);
+            R(p, p - 1) = 0.0;
+        }
+    }
+    // 4. exact zeros below the patterns
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j + 1 < i; ++j) H(i, j) = 0.0;
+        for (int j = 0; j < i; ++j) R(i, j) = 0.0;
+    }
+    for (int i = 2; i < n; ++i)
+        if (H(i, i - 1) != 0.0 && H(i - 1, i - 2) != 0.0) {
+            err = "internal: consecutive nonzero subdiagonals after QZ";
+            return TT_EINVAL;
+        }
+    if (singular(0, n - 1)) {
+        err = "C is singular to working precision (infinite generalized eigenvalue)";
+        return TT_ESINGULAR;
+    }
+    std::memcpy(Sout, H.a.data(), sizeof(double) * (size_t)n * n);
+    std::memcpy(Tout, R.a.data(), sizeof(double) * (size_t)n * n);
+    std::memcpy(Qout, Q.a.data(), sizeof(double) * (size_t)n * n);
+    std::memcpy(Zout, Z.a.data(), sizeof(double) * (size_t)n * n);
+    return TT_OK;
+}
+
 }  // namespace
 
 int schur_real(int n, const double* A, double* T, double* U, std::string& err) {
     if (n <= 0) return TT_OK;
     return schur_one(n, A, T, U, err);
+}
+
+int qz_real(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z,
+            std::string& err) {
+    if (n <= 0) return TT_OK;
+    return qz_one(n, A, C, S, T, Q, Z, err);
 }
 
 // Several independent decompositions (one per mode) on host threads.

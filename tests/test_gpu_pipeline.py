@@ -270,6 +270,24 @@ def test_mixed_precision_first_correction_is_fp32_sized():
     assert rel(host(X), oracle.lap_solve(p["T"], p["B"])) <= 1e-9
 
 
+# ---------------------------------------------------------------- dense pairs (host QZ)
+@pytest.mark.parametrize("shape,seed", [((24, 31, 17), 1), ((12, 9, 14, 11), 2), ((40, 40, 40), 3),
+                                        ((50, 45), 4), ((1, 7, 3), 5), ((48, 40, 36, 32), 6)])
+def test_general_pair_matches_oracle(shape, seed):
+    """Dense (A_mu, C_mu): host QZ, GPU transforms and triangular solve, against
+    the oracle's solve through the generator's own generalized Schur factors."""
+    p = ti.pair_dense(shape, seed=seed)
+    print("case general_pair", shape, seed, flush=True)
+    X_ref = oracle.pair_dense_solve_with_factors(p["Q"], p["S"], p["T"], p["Z"], p["B"])
+    B = dev(p["B"])
+    X = torch.empty_like(B)
+    plan = tt().Plan(p["A"], B.shape, C=p["C"], general=True)
+    plan.solve(B, X)
+    plan.status()
+    assert rel(host(X), X_ref) < TOL
+    plan.close()
+
+
 # ---------------------------------------------------------------- per-wave profile
 def test_profile_waves_timeline():
     """The per-wave profile runs the same solve (identical X) and its wave

@@ -356,3 +356,14 @@ def test_dense_with_factors_vs_dense():
     X = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
     Xd = unvecF(np.linalg.solve(laplace_dense(p["A"]), vecF(p["B"])), p["B"].shape)
     assert rel(X, Xd) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 7), (3, 5, 4, 2), (9, 8)])
+def test_pair_dense_with_factors_vs_dense(shape):
+    """Dense pair form (Sec. 3) through known generalized Schur factors
+    against the assembled Kronecker operator (eq. 1.4 for pairs)."""
+    p = ti.pair_dense(shape, seed=41, bumps="random")
+    X = oracle.pair_dense_solve_with_factors(p["Q"], p["S"], p["T"], p["Z"], p["B"])
+    Xd = unvecF(np.linalg.solve(pair_dense(p["A"], p["C"]), vecF(p["B"])), p["B"].shape)
+    assert rel(X, Xd) < 1e-12
+    assert rel(oracle.pair_apply(p["A"], p["C"], X), p["B"]) < 1e-13

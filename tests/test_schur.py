@@ -1,6 +1,7 @@
 """Host real Schur decomposition (the host step of Algorithm 1): A = U T U^T
 with U orthogonal and T upper quasi-triangular in standard form.  CPU only."""
 import numpy as np
+import scipy.linalg as sla
 import pytest
 
 import tt_inputs as ti
@@ -132,3 +133,120 @@ def test_non_finite_rejected():
     A[1, 2] = np.nan
     with pytest.raises(tt().TTError):
         tt().schur_host(A)
+
+
+# ---------------------------------------------------------------- QZ (Sec. 3)
+def check_qz(A, C, S, T, Q, Z, c=50.0):
+    n = A.shape[0]
+    assert np.linalg.norm(A - Q @ S @ Z.T) <= c * max(n, 1) * U64 * max(np.linalg.norm(A), 1e-300)
+    assert np.linalg.norm(C - Q @ T @ Z.T) <= c * max(n, 1) * U64 * max(np.linalg.norm(C), 1e-300)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= c * max(n, 1) * U64
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) <= c * max(n, 1) * U64
+    assert np.all(np.tril(T, -1) == 0.0)
+    assert np.all(np.tril(S, -2) == 0.0)
+    nz = np.nonzero(np.diag(S, -1))[0]
+    assert np.all(np.diff(nz) >= 2), "two consecutive nonzero subdiagonal entries"
+    # a 2x2 block is kept only for a complex pair
+    for k in nz:
+        ev = sla.eigvals(S[k:k + 2, k:k + 2], T[k:k + 2, k:k + 2])
+        assert abs(ev[0].imag) > 0.0
+    return nz
+
+
+def pencil_eigs(S, T):
+    n, ev, k = S.shape[0], [], 0
+    while k < n:
+        if k + 1 < n and S[k + 1, k] != 0.0:
+            ev += list(sla.eigvals(S[k:k + 2, k:k + 2], T[k:k + 2, k:k + 2]))
+            k += 2
+        else:
+            ev.append(S[k, k] / T[k, k])
+            k += 1
+    return np.array(ev, dtype=complex)
+
+
+def match_eigs(ev, ref):
+    ev, worst = list(ev), 0.0
+    for r in ref:
+        d = [abs(r - e) for e in ev]
+        j = int(np.argmin(d))
+        worst = max(worst, d[j] / max(1.0, abs(r)))
+        ev.pop(j)
+    return worst
+
+
+def _pencils():
+    g = np.random.default_rng(5)
+    out = []
+    for n in (1, 2, 3, 5, 17, 64):
+        out.append(("random", g.normal(size=(n, n)), g.normal(size=(n, n)) + 2.0 * np.eye(n)))
+    n = 40
+    M = g.normal(size=(n, n))
+    out.append(("symmetric A, C = I", M + M.T, np.eye(n)))
+    out.append(("upper triangular C", g.normal(size=(n, n)), np.triu(g.normal(size=(n, n))) + 3.0 * np.eye(n)))
+    k = 12
+    Ar = np.zeros((2 * k, 2 * k))
+    for i in range(k):
+        Ar[2 * i:2 * i + 2, 2 * i:2 * i + 2] = [[1.0 + 0.1 * i, 2.0], [-2.0, 1.0 + 0.1 * i]]
+    Qr = ti.random_orthogonal(2 * k, g)
+    out.append(("complex pairs only", Qr @ Ar @ Qr.T, np.eye(2 * k) + 0.05 * g.normal(size=(2 * k, 2 * k))))
+    p = ti.pair_dense((30, 24), seed=3)
+    out.append(("generated dense pair", p["A"][0], p["C"][0]))
+    return out
+
+
+@pytest.mark.parametrize("case", _pencils(), ids=lambda c: f"{c[0]}-{c[1].shape[0]}")
+def test_qz_properties_and_eigenvalues(case):
+    """A = Q S Z^T, C = Q T Z^T, orthogonal factors, the patterns of the
+    generalized real Schur form, and the pencil's eigenvalues against
+    scipy.linalg.eigvals(A, C)."""
+    _, A, C = case
+    S, T, Q, Z = tt().qz_host(A, C)
+    nz = check_qz(A, C, S, T, Q, Z)
+    # the generated pencil has clustered non-normal eigenvalues (condition
+    # ~1e8): its eigenvalues agree only to what that allows; QZ's guarantee
+    # is the backward error checked above
+    tol = 1e-6 if case[0] == "generated dense pair" else 1e-10
+    assert match_eigs(pencil_eigs(S, T), sla.eigvals(A, C)) < tol
+    if case[0] == "symmetric A, C = I":
+        assert len(nz) == 0
+    if case[0] == "complex pairs only":
+        assert len(nz) == A.shape[0] // 2
+
+
+def test_qz_identity_C_gives_real_schur_spectrum():
+    A = ti.laplace_dense((20, 3, 3), seed=8)["A"][0]
+    S, T, Q, Z = tt().qz_host(A, np.eye(20))
+    check_qz(A, np.eye(20), S, T, Q, Z)
+    assert match_eigs(pencil_eigs(S, T), np.linalg.eigvals(A)) < 1e-10
+
+
+def test_qz_errors():
+    g = np.random.default_rng(2)
+    C = g.normal(size=(9, 9))
+    C[:, 4] = 0.0
+    with pytest.raises(tt().TTError, match="singular"):
+        tt().qz_host(g.normal(size=(9, 9)), C)
+    A = g.normal(size=(5, 5))
+    A[1, 2] = np.inf
+    with pytest.raises(tt().TTError):
+        tt().qz_host(A, np.eye(5))
+
+
+def test_general_pair_plan_rejects_singular_C():
+    """The dense-pair plan fails on the host (before any device work) when
+    some C_mu is singular."""
+    import ctypes
+    m = tt()
+    p = ti.pair_dense((6, 5, 4), seed=4)
+    C = [c.copy() for c in p["C"]]
+    C[1][:, 0] = 0.0
+    _, ap = m._host_mats(p["A"])
+    _, cp = m._host_mats(C)
+    o = m.Opts()
+    m.lib().tt_opts_default(ctypes.byref(o))
+    h = ctypes.c_void_p()
+    rc = m.lib().tt_plan_create_general_pair(ctypes.byref(h), 3, m._shape((6, 5, 4)), ap, cp, ctypes.byref(o))
+    assert rc == m.TT_ESINGULAR
+    assert not h.value
+    assert b"singular" in m.lib().tt_last_error()

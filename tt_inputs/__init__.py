@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import numpy as np
 
-ROLE_T, ROLE_Q, ROLE_C, ROLE_B, ROLE_G, ROLE_DIR, ROLE_SHAPE = 0, 1, 2, 3, 4, 5, 6
+ROLE_T, ROLE_Q, ROLE_C, ROLE_B, ROLE_G, ROLE_DIR, ROLE_SHAPE, ROLE_Z = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 def rng(seed: int, role: int, mu: int = 0, item: int = 0) -> np.random.Generator:
@@ -148,6 +148,18 @@ def pair_tri(shape, seed=0, bumps="every8"):
     C = [upper_triangular(n, rng(seed, ROLE_C, mu)) for mu, n in enumerate(shape)]
     B = gaussian_tensor(shape, rng(seed, ROLE_B))
     return {"A": A, "C": C, "B": B}
+
+
+def pair_dense(shape, seed=0, bumps="every8"):
+    """Dense pair form: A_mu = Q_mu S_mu Z_mu^T, C_mu = Q_mu T_mu Z_mu^T with
+    (S_mu, T_mu) the triangular pair of pair_tri and Q_mu, Z_mu random
+    orthogonal (so the generalized Schur factors are known)."""
+    p = pair_tri(shape, seed, bumps)
+    Q = [random_orthogonal(a.shape[0], rng(seed, ROLE_Q, mu)) for mu, a in enumerate(p["A"])]
+    Z = [random_orthogonal(a.shape[0], rng(seed, ROLE_Z, mu)) for mu, a in enumerate(p["A"])]
+    Ad = [np.ascontiguousarray(q @ a @ z.T) for q, a, z in zip(Q, p["A"], Z)]
+    Cd = [np.ascontiguousarray(q @ c @ z.T) for q, c, z in zip(Q, p["C"], Z)]
+    return {"A": Ad, "C": Cd, "B": p["B"], "S": p["A"], "T": p["C"], "Q": Q, "Z": Z}
 
 
 def uneven_batch(count=64, lo=32, hi=192, seed=0, d=3, bumps="every8"):
