@@ -222,6 +222,21 @@ __device__ inline double lds_dot(const double* L, int to, int xo, int xs, int le
     return a0 + a1;
 }
 
+// The same sum split over a pair of lanes: lane q of the pair takes the terms
+// j = q, q + 2, ...; T past the row end is the first zero of its padding.
+__device__ inline double lds_dot_pair(const double* L, int to, int xo, int xs, int len, int q) {
+    double a0 = 0.0, a1 = 0.0;
+    const int last = xo + (len - 1) * xs, tz = to + len;
+    for (int j = q; j < len; j += 8) {
+        const int x0 = xo + j * xs;
+        a0 = fma(L[to + j], L[x0], a0);
+        a1 = fma(L[min(to + j + 2, tz)], L[min(x0 + 2 * xs, last)], a1);
+        a0 = fma(L[min(to + j + 4, tz)], L[min(x0 + 4 * xs, last)], a0);
+        a1 = fma(L[min(to + j + 6, tz)], L[min(x0 + 6 * xs, last)], a1);
+    }
+    return a0 + a1;
+}
+
 // Small system of a tuple with 2x2 blocks in some modes (a: first rows,
 // w: widths); the right-hand sides of its unknowns are already in Xs.
 template <int D>
@@ -377,6 +392,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                                                       LeafGeom geom) {
     extern __shared__ double lds[];
     const int tid = threadIdx.x;
+    constexpr int LPE = (NT > kLeafNT) ? 2 : 1;  // lanes per unknown in the dot products
     const LeafDesc L = leaves[first + blockIdx.x];
     const ProbDesc& P = probs[L.prob];
 
@@ -698,7 +714,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
             pne = decode(cen, a, w);
             if (pne <= 4 && !tuple_inverse<D>(Ts, tp, ls, a, w, Mi, peq)) ok = false;
         }
-        for (int i = ebeg + tid; i < eend; i += NT) {
+        // LPE lanes per unknown: both lanes of a pair take the same unknown,
+        // so they stay converged for the exchange of their partial sums
+        for (int i = ebeg + tid / LPE; i < eend; i += NT / LPE) {
             const uint32_t r = rec[i];
             int c[D], e = 0;
 #pragma unroll
@@ -715,15 +733,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                 single = single && !(b2 & 2);
                 const int dg = toff[mu] + c[mu] * (tp[mu] + 1);
                 cd += lds[dg];
-                acc += lds_dot(lds, dg + gap, e + gap * ls[mu], ls[mu], sz[mu] - c[mu] - gap);
+                if constexpr (LPE == 1)
+                    acc += lds_dot(lds, dg + gap, e + gap * ls[mu], ls[mu], sz[mu] - c[mu] - gap);
+                else
+                    acc += lds_dot_pair(lds, dg + gap, e + gap * ls[mu], ls[mu], sz[mu] - c[mu] - gap, tid & 1);
             }
-            const double rhs = lds[e] - acc;
-            if (single) {
-                const double x = rhs / cd;
-                if (cd == 0.0 || !isfinite(x)) ok = false;
-                lds[e] = x;
-            } else {
-                lds[e] = rhs;
+            if constexpr (LPE == 2) acc += __shfl_xor(acc, 1);
+            if (LPE == 1 || (tid & 1) == 0) {
+                const double rhs = lds[e] - acc;
+                if (single) {
+                    const double x = rhs / cd;
+                    if (cd == 0.0 || !isfinite(x)) ok = false;
+                    lds[e] = x;
+                } else {
+                    lds[e] = rhs;
+                }
             }
         }
         if (cend > cbeg) {  // uniform
@@ -791,7 +815,7 @@ LeafGeom leaf_geometry(int D, const int* bmax, int maxtup, int maxcpl, int maxH)
 int leaf_lds_bytes(int D, const int* bmax, int maxtup, int maxcpl, int maxH) {
     const LeafGeom g = leaf_geometry(D, bmax, maxtup, maxcpl, maxH);
     return (g.cap + g.tsum + g.uwords + D) * (int)sizeof(double) + (D + 1) * (int)sizeof(uint32_t) +
-           (3 * (maxH + 1) + kLeafNT / 64) * (int)sizeof(int32_t);
+           (3 * (maxH + 1) + kLeafNTWide / 64) * (int)sizeof(int32_t);
 }
 
 hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
@@ -801,14 +825,32 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     const int lds = leaf_lds_bytes(D, bmax, maxtup, maxcpl, maxH);
     const LeafGeom geom = leaf_geometry(D, bmax, maxtup, maxcpl, maxH);
     const bool small = geom.cap <= 1000;
-    dim3 grid((unsigned)count), block(small ? 64 : kLeafNT);
-    const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64> : (const void*)leaf_kernel<3, kLeafNT>)
+    // a launch with at most one leaf per CU gives each order-3 leaf 512
+    // threads (two lanes per unknown): the CU would otherwise hold one
+    // 256-thread leaf and idle
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = -1;
+    }
+    const bool wide = D == 3 && !small && cus > 0 && count <= cus;
+    dim3 grid((unsigned)count), block(small ? 64 : (wide ? kLeafNTWide : kLeafNT));
+    const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64>
+                                       : (wide ? (const void*)leaf_kernel<3, kLeafNTWide>
+                                               : (const void*)leaf_kernel<3, kLeafNT>))
                               : (small ? (const void*)leaf_kernel<4, 64> : (const void*)leaf_kernel<4, kLeafNT>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    if (D == 3 && small)
+    if (wide)
+        hipLaunchKernelGGL((leaf_kernel<3, kLeafNTWide>), grid, block, lds, st, leaves, first, probs, shapes, ents,
+                           hoffs, status, geom);
+    else if (D == 3 && small)
         hipLaunchKernelGGL((leaf_kernel<3, 64>), grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs,
                            status, geom);
     else if (D == 3)
