@@ -828,15 +828,10 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     // a launch with at most one leaf per CU gives each order-3 leaf 512
     // threads (two lanes per unknown): the CU would otherwise hold one
     // 256-thread leaf and idle
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            cus = v;
-        else
-            cus = -1;
-    }
+    int cus = 0, dev = 0;  // CUs of the current device (queried per launch: a process may drive several GPUs)
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
     const bool wide = D == 3 && !small && cus > 0 && count <= cus;
     dim3 grid((unsigned)count), block(small ? 64 : (wide ? kLeafNTWide : kLeafNT));
     const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64>
