@@ -207,7 +207,20 @@ def extras(args):
     msf = _timed(lambda: plan.solve(Bs, Xs), steps, 1)
     plan.status()
     msb = _timed(lambda: tt.solve_backward_batched(T, Xs, Gs), steps, 1)
-    out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "forward_flops": plan.flops}
+    # the same backward with a reusable adjoint plan (planning and workspace
+    # allocation outside the timed region, as in a training loop)
+    planb = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs], trans=True)
+    dBs = [torch.empty_like(g) for g in Gs]
+    dTs = [[torch.empty_like(t) for t in Tb] for Tb in T]
+
+    def backward():
+        planb.solve(Gs, dBs)
+        planb.coefficient_grads(T, Xs, dBs, dTs)
+
+    msbp = _timed(backward, steps, 1)
+    planb.status()
+    out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "ms_backward_plan": msbp,
+                              "forward_flops": plan.flops}
     return out
 
 

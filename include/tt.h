@@ -155,6 +155,7 @@ int solve_backward_batched(int count, const int* d, const int64_t* const* n,
                            double* const* dB, double* const* const* dT,
                            int dense_grad, tt_opts* opts);
 
+
 /* ---------------------------------------------------------------------------
  * Plans: the split/merge schedule and the coefficient structure of
  * solve_tri_tensor, built once and executed many times (host work and the
@@ -195,6 +196,20 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n,
  * precision), TT_ENOMEM. */
 int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
                                 const double* const* C_host, const tt_opts* opts);
+
+/* Coefficient gradients with a reusable plan (the adjoint's second half):
+ * for every problem i of a triangular plan (tt_plan_create /
+ * tt_plan_create_batched, typically the adjoint plan trans = 1 whose solve
+ * gave Lam), dT[i][mu] = -Lam_(mu) X_(mu)^T for mu < d_i, masked to the
+ * quasi-triangular pattern of T[i][mu] unless dense_grad.  T[i][mu]: the
+ * problem's device coefficients (n_mu x n_mu row-major), X[i], Lam[i]: device
+ * tensors of the problem's shape, dT[i][mu]: device n_mu x n_mu outputs
+ * (dT[i] NULL skips problem i).  Enqueued on stream; the split-K workspace is
+ * allocated by the plan on first use (and grown when a call needs more).
+ * Errors: TT_EINVAL (NULL arguments, a pair-form or dense-coefficient plan),
+ * TT_ENOMEM. */
+int tt_plan_coefficient_grads(tt_plan plan, const double* const* const* T, const double* const* X,
+                              const double* const* Lam, double* const* const* dT, int dense_grad, void* stream);
 int tt_plan_create_batched(tt_plan* out, int count, const int* d,
                            const int64_t* const* n, const double* const* const* T,
                            int trans, const tt_opts* opts);

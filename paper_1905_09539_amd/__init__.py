@@ -44,7 +44,7 @@ SYMBOLS = [
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
-    "tt_plan_create_general_pair",
+    "tt_plan_create_general_pair", "tt_plan_coefficient_grads",
 ]
 
 
@@ -81,6 +81,7 @@ def lib():
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.tt_schur_host.argtypes = [ctypes.c_int, vp, vp, vp]
         L.tt_qz_host.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.tt_plan_coefficient_grads.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.tt_plan_create_general_pair.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp,
                                                   ctypes.POINTER(Opts)]
         L.tt_plan_profile_waves.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -289,6 +290,27 @@ class Plan:
         xp = _ptr_array([_dev(x) for x in X])
         _check(lib().tt_plan_solve_batched(self._h, bp, xp, _stream(stream)))
         return X
+
+    def coefficient_grads(self, T, X, Lam, dT=None, dense_grad=False, stream=None):
+        """dT[mu] = -Lam_(mu) X_(mu)^T (masked to the pattern of T[mu] unless
+        dense_grad) for every problem of this triangular plan.  Single plans:
+        T a coefficient list, X and Lam tensors; batched plans: lists of
+        those.  Returns dT (lists of n_mu x n_mu tensors)."""
+        import torch
+        single = self.count == 1 and torch.is_tensor(X)
+        Tb, Xb, Lb = ([T], [X], [Lam]) if single else (T, X, Lam)
+        if dT is None:
+            dT = [[torch.empty_like(t) for t in Ti] for Ti in Tb]
+        elif single:
+            dT = [dT]
+        tarrs = [_ptr_array([_dev(t) for t in Ti]) for Ti in Tb]
+        darrs = [_ptr_array([_dev(t) for t in Di]) for Di in dT]
+        t_arr = (ctypes.c_void_p * len(tarrs))(*[ctypes.cast(a, ctypes.c_void_p).value for a in tarrs])
+        d_arr = (ctypes.c_void_p * len(darrs))(*[ctypes.cast(a, ctypes.c_void_p).value for a in darrs])
+        _check(lib().tt_plan_coefficient_grads(self._h, t_arr, _ptr_array([_dev(x) for x in Xb]),
+                                               _ptr_array([_dev(l) for l in Lb]), d_arr, int(bool(dense_grad)),
+                                               _stream(stream)))
+        return dT[0] if single else dT
 
     def profile(self, B, X, stream=None, serial=False):
         """Run one solve with timing events around every launch (on the

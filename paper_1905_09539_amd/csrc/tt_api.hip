@@ -95,6 +95,9 @@ struct tt_plan_s {
     std::vector<double*> pre, post;
     double* W = nullptr;
     double pipe_flops = 0;
+    // coefficient gradients: split-K Gram workspace (allocated on first use)
+    double* gW = nullptr;
+    size_t gW_size = 0;
     // mixed precision with FP64 refinement (dense coefficients)
     int prec = TT_FP64;
     double tol = 1e-13;
@@ -112,6 +115,7 @@ struct tt_plan_s {
         if (ev_start) (void)hipEventDestroy(ev_start);
         if (side) (void)hipStreamDestroy(side);
         for (void* p : owned) (void)hipFree(p);
+        if (gW) (void)hipFree(gW);
         if (d_probs) (void)hipFree(d_probs);
         if (d_leaves) (void)hipFree(d_leaves);
         if (d_shapes) (void)hipFree(d_shapes);
@@ -1009,6 +1013,41 @@ static size_t grad_workspace(int d, const int64_t* n) {
         w = std::max(w, ns * (size_t)(n[mu] * n[mu]));
     }
     return w;
+}
+
+int tt_plan_coefficient_grads(tt_plan plan, const double* const* const* T, const double* const* X,
+                              const double* const* Lam, double* const* const* dT, int dense_grad, void* stream) {
+    if (!plan || !T || !X || !Lam || !dT) return fail(TT_EINVAL, "NULL argument");
+    if (plan->kind != KIND_TRI) return fail(TT_EINVAL, "coefficient gradients need a triangular plan");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<std::vector<int64_t>> nu((size_t)plan->count);
+    size_t wmax = 1;
+    for (int i = 0; i < plan->count; ++i) {
+        const HostProblem& hp = plan->sched.probs[(size_t)i];
+        const int lead = hp.D - hp.d_user;
+        for (int mu = 0; mu < hp.d_user; ++mu) nu[(size_t)i].push_back(hp.n[lead + mu]);
+        if (dT[i]) wmax = std::max(wmax, grad_workspace(hp.d_user, nu[(size_t)i].data()));
+    }
+    if (wmax > plan->gW_size) {
+        if (plan->gW) {
+            TT_HIP_CHECK(hipStreamSynchronize(st));
+            TT_HIP_CHECK(hipFree(plan->gW));
+            plan->gW = nullptr;
+            plan->gW_size = 0;
+        }
+        if (hipMalloc((void**)&plan->gW, sizeof(double) * wmax) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
+        plan->gW_size = wmax;
+    }
+    plan->last_stream = st;
+    for (int i = 0; i < plan->count; ++i) {
+        if (!dT[i]) continue;
+        const HostProblem& hp = plan->sched.probs[(size_t)i];
+        if (hp.N == 0) continue;
+        if (!T[i] || !X[i] || !Lam[i]) return fail(TT_EINVAL, "tensor or coefficient pointer is NULL");
+        int rc = coefficient_grads(hp.d_user, nu[(size_t)i].data(), T[i], Lam[i], X[i], dT[i], dense_grad, plan->gW, st);
+        if (rc) return rc;
+    }
+    return TT_OK;
 }
 
 int solve_backward_batched(int count, const int* d, const int64_t* const* n,

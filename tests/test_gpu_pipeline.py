@@ -270,6 +270,41 @@ def test_mixed_precision_first_correction_is_fp32_sized():
     assert rel(host(X), oracle.lap_solve(p["T"], p["B"])) <= 1e-9
 
 
+def test_plan_coefficient_grads():
+    """Reusable adjoint plan: its solve plus tt_plan_coefficient_grads give
+    exactly the one-shot backward (same kernels), twice in a row on one plan
+    (workspace reuse), and a single-problem plan matches the oracle."""
+    probs = ti.uneven_batch(5, 20, 48, seed=11)
+    print("case plan coefficient grads", flush=True)
+    T = [[dev(t) for t in q["T"]] for q in probs]
+    Xs = [dev(q["B"]) for q in probs]  # any tensors: dT is linear in X
+    Gs = [dev(q["G"]) for q in probs]
+    dB1, dT1 = tt().solve_backward_batched(T, Xs, Gs)
+    plan = tt().Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs], trans=True)
+    for _ in range(2):
+        dB2 = plan.solve(Gs)
+        dT2 = plan.coefficient_grads(T, Xs, dB2)
+        plan.status()
+        for b in range(len(probs)):
+            assert torch.equal(dB1[b], dB2[b])
+            for mu in range(3):
+                assert torch.equal(dT1[b][mu], dT2[b][mu])
+    plan.close()
+    q = ti.laplace_tri((40, 33, 27), seed=12)
+    T0 = [dev(t) for t in q["T"]]
+    G = dev(q["B"])
+    Xo = oracle.lap_solve(q["T"], q["B"])
+    p1 = tt().Plan(T0, G.shape, trans=True)
+    Lam = p1.solve(G)
+    dT = p1.coefficient_grads(T0, dev(Xo), Lam)
+    p1.status()
+    Lo = oracle.lap_solve(q["T"], q["B"], trans=True)
+    assert rel(host(Lam), Lo) <= TOL
+    for mu in range(3):
+        assert rel(host(dT[mu]), oracle.grad_T(q["T"], Lo, Xo, mu)) <= TOL
+    p1.close()
+
+
 # ---------------------------------------------------------------- dense pairs (host QZ)
 @pytest.mark.parametrize("shape,seed", [((24, 31, 17), 1), ((12, 9, 14, 11), 2), ((40, 40, 40), 3),
                                         ((50, 45), 4), ((1, 7, 3), 5), ((48, 40, 36, 32), 6)])
