@@ -95,9 +95,15 @@ struct tt_plan_s {
     std::vector<double*> pre, post;
     double* W = nullptr;
     double pipe_flops = 0;
-    // coefficient gradients: split-K Gram workspace (allocated on first use)
+    // coefficient gradients (allocated on first use): split-K Gram workspace,
+    // the job table (pinned host staging + device copy) and an event marking
+    // the end of its last upload
     double* gW = nullptr;
     size_t gW_size = 0;
+    GramJob* gJobsHost = nullptr;
+    GramJob* gJobsDev = nullptr;
+    int gJobsCap = 0;
+    hipEvent_t gJobsEv = nullptr;
     // mixed precision with FP64 refinement (dense coefficients)
     int prec = TT_FP64;
     double tol = 1e-13;
@@ -116,6 +122,9 @@ struct tt_plan_s {
         if (side) (void)hipStreamDestroy(side);
         for (void* p : owned) (void)hipFree(p);
         if (gW) (void)hipFree(gW);
+        if (gJobsDev) (void)hipFree(gJobsDev);
+        if (gJobsHost) (void)hipHostFree(gJobsHost);
+        if (gJobsEv) (void)hipEventDestroy(gJobsEv);
         if (d_probs) (void)hipFree(d_probs);
         if (d_leaves) (void)hipFree(d_leaves);
         if (d_shapes) (void)hipFree(d_shapes);
@@ -985,34 +994,96 @@ int solve_general_tensor(int d, const int64_t* n, const double* const* A_host, c
 
 // Coefficient gradients of one problem: dT[mu] = -Lam_(mu) X_(mu)^T, masked
 // to the pattern of T[mu] unless dense.  W: split-K workspace.
-static int coefficient_grads(int d, const int64_t* n, const double* const* T, const double* Lam, const double* X,
-                             double* const* dT, int dense, double* W, hipStream_t st) {
-    int64_t N = 1;
-    for (int mu = 0; mu < d; ++mu) N *= n[mu];
-    for (int mu = 0; mu < d; ++mu) {
-        if (!dT[mu] || n[mu] == 0) continue;
-        int64_t L = 1, R = 1;
-        for (int nu = 0; nu < d; ++nu) {
-            if (nu < mu) L *= n[nu];
-            if (nu > mu) R *= n[nu];
+// dT[i][mu] = -Lam_i (mu) X_i (mu)^T (masked unless dense) for every problem i
+// with dT[i] != NULL, as two batched launches over all (problem, mode) pairs.
+static int grads_batched(tt_plan_s* P, const double* const* const* T, const double* const* X,
+                         const double* const* Lam, double* const* const* dT, int dense_grad, hipStream_t st) {
+    std::vector<GramJob> jobs;
+    int64_t tiles = 0;
+    for (int i = 0; i < P->count; ++i) {
+        if (!dT[i]) continue;
+        const HostProblem& hp = P->sched.probs[(size_t)i];
+        if (hp.N == 0) continue;
+        if (!T[i] || !X[i] || !Lam[i]) return fail(TT_EINVAL, "tensor or coefficient pointer is NULL");
+        const int lead = hp.D - hp.d_user;
+        for (int mu = 0; mu < hp.d_user; ++mu) {
+            const int n = (int)hp.n[lead + mu];
+            if (!dT[i][mu] || n == 0) continue;
+            if (!T[i][mu]) return fail(TT_EINVAL, "coefficient pointer is NULL");
+            GramJob J{};
+            J.P = Lam[i];
+            J.Q = X[i];
+            J.T = T[i][mu];
+            J.out = dT[i][mu];
+            J.n = n;
+            J.dense = dense_grad;
+            J.L = 1;
+            J.R = 1;
+            for (int nu = 0; nu < hp.d_user; ++nu) {
+                if (nu < mu) J.L *= hp.n[lead + nu];
+                if (nu > mu) J.R *= hp.n[lead + nu];
+            }
+            const int nt = (n + kGramTile - 1) / kGramTile;
+            tiles += (int64_t)nt * nt;
+            jobs.push_back(J);
         }
-        const int ns = gram_splits((int)n[mu], L * R);
-        TT_HIP_CHECK(launch_gram(Lam, X, W, ns, (int)n[mu], L, R, st));
-        TT_HIP_CHECK(launch_gram_reduce(W, ns, (int)n[mu], T[mu], dense, -1.0, dT[mu], st));
     }
+    if (jobs.empty()) return TT_OK;
+    // split K so that the whole batch has ~4096 workgroups, at least 512
+    // terms per split
+    const int64_t want = std::max<int64_t>(1, 4096 / std::max<int64_t>(tiles, 1));
+    int64_t wg = 0, el = 0;
+    size_t ws = 0;
+    std::vector<size_t> woff;
+    for (GramJob& J : jobs) {
+        const int64_t K = J.L * J.R;
+        int64_t ns = std::min<int64_t>(want, std::max<int64_t>(1, K / 512));
+        int64_t kc = (K + ns - 1) / ns;
+        kc = (kc + kGramKC - 1) / kGramKC * kGramKC;
+        ns = (K + kc - 1) / kc;
+        J.nsplit = (int)ns;
+        J.kchunk = kc;
+        J.wg_first = wg;
+        J.el_first = el;
+        woff.push_back(ws);
+        const int nt = (J.n + kGramTile - 1) / kGramTile;
+        wg += (int64_t)nt * nt * ns;
+        el += (int64_t)J.n * J.n;
+        ws += (size_t)ns * (size_t)J.n * (size_t)J.n;
+    }
+    if (ws > P->gW_size) {
+        if (P->gW) {
+            TT_HIP_CHECK(hipStreamSynchronize(st));
+            TT_HIP_CHECK(hipFree(P->gW));
+            P->gW = nullptr;
+            P->gW_size = 0;
+        }
+        if (hipMalloc((void**)&P->gW, sizeof(double) * ws) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
+        P->gW_size = ws;
+    }
+    for (size_t j = 0; j < jobs.size(); ++j) jobs[j].W = P->gW + woff[j];
+    const int nj = (int)jobs.size();
+    if (!P->gJobsEv) TT_HIP_CHECK(hipEventCreateWithFlags(&P->gJobsEv, hipEventDisableTiming));
+    TT_HIP_CHECK(hipEventSynchronize(P->gJobsEv));  // the previous upload has read the staging buffer
+    if (nj > P->gJobsCap) {
+        if (P->gJobsDev) {
+            TT_HIP_CHECK(hipStreamSynchronize(st));
+            TT_HIP_CHECK(hipFree(P->gJobsDev));
+            P->gJobsDev = nullptr;
+        }
+        if (P->gJobsHost) TT_HIP_CHECK(hipHostFree(P->gJobsHost));
+        P->gJobsHost = nullptr;
+        P->gJobsCap = 0;
+        if (hipHostMalloc((void**)&P->gJobsHost, sizeof(GramJob) * nj, 0) != hipSuccess ||
+            hipMalloc((void**)&P->gJobsDev, sizeof(GramJob) * nj) != hipSuccess)
+            return fail(TT_ENOMEM, "allocation of the gradient job table failed");
+        P->gJobsCap = nj;
+    }
+    std::memcpy(P->gJobsHost, jobs.data(), sizeof(GramJob) * nj);
+    TT_HIP_CHECK(hipMemcpyAsync(P->gJobsDev, P->gJobsHost, sizeof(GramJob) * nj, hipMemcpyHostToDevice, st));
+    TT_HIP_CHECK(hipEventRecord(P->gJobsEv, st));
+    TT_HIP_CHECK(launch_gram_batched(P->gJobsDev, nj, wg, el, -1.0, st));
     return TT_OK;
-}
-
-static size_t grad_workspace(int d, const int64_t* n) {
-    int64_t N = 1;
-    for (int mu = 0; mu < d; ++mu) N *= n[mu];
-    size_t w = 1;
-    for (int mu = 0; mu < d; ++mu) {
-        if (n[mu] == 0) continue;
-        const size_t ns = (size_t)gram_splits((int)n[mu], N / n[mu]);
-        w = std::max(w, ns * (size_t)(n[mu] * n[mu]));
-    }
-    return w;
 }
 
 int tt_plan_coefficient_grads(tt_plan plan, const double* const* const* T, const double* const* X,
@@ -1020,34 +1091,8 @@ int tt_plan_coefficient_grads(tt_plan plan, const double* const* const* T, const
     if (!plan || !T || !X || !Lam || !dT) return fail(TT_EINVAL, "NULL argument");
     if (plan->kind != KIND_TRI) return fail(TT_EINVAL, "coefficient gradients need a triangular plan");
     hipStream_t st = (hipStream_t)stream;
-    std::vector<std::vector<int64_t>> nu((size_t)plan->count);
-    size_t wmax = 1;
-    for (int i = 0; i < plan->count; ++i) {
-        const HostProblem& hp = plan->sched.probs[(size_t)i];
-        const int lead = hp.D - hp.d_user;
-        for (int mu = 0; mu < hp.d_user; ++mu) nu[(size_t)i].push_back(hp.n[lead + mu]);
-        if (dT[i]) wmax = std::max(wmax, grad_workspace(hp.d_user, nu[(size_t)i].data()));
-    }
-    if (wmax > plan->gW_size) {
-        if (plan->gW) {
-            TT_HIP_CHECK(hipStreamSynchronize(st));
-            TT_HIP_CHECK(hipFree(plan->gW));
-            plan->gW = nullptr;
-            plan->gW_size = 0;
-        }
-        if (hipMalloc((void**)&plan->gW, sizeof(double) * wmax) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-        plan->gW_size = wmax;
-    }
     plan->last_stream = st;
-    for (int i = 0; i < plan->count; ++i) {
-        if (!dT[i]) continue;
-        const HostProblem& hp = plan->sched.probs[(size_t)i];
-        if (hp.N == 0) continue;
-        if (!T[i] || !X[i] || !Lam[i]) return fail(TT_EINVAL, "tensor or coefficient pointer is NULL");
-        int rc = coefficient_grads(hp.d_user, nu[(size_t)i].data(), T[i], Lam[i], X[i], dT[i], dense_grad, plan->gW, st);
-        if (rc) return rc;
-    }
-    return TT_OK;
+    return grads_batched(plan, T, X, Lam, dT, dense_grad, st);
 }
 
 int solve_backward_batched(int count, const int* d, const int64_t* const* n,
@@ -1064,17 +1109,8 @@ int solve_backward_batched(int count, const int* d, const int64_t* const* n,
     // Lam: sum_mu Lam x_mu T_mu^T = G, into dB
     if ((rc = tt_plan_solve_batched(p, G, dB, st))) return rc;
     if (dT) {
-        size_t wmax = 1;
-        for (int i = 0; i < count; ++i)
-            if (dT[i]) wmax = std::max(wmax, grad_workspace(d[i], n[i]));
-        double* W = nullptr;
-        if (hipMalloc((void**)&W, sizeof(double) * wmax) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-        p->owned.push_back(W);
-        for (int i = 0; i < count; ++i) {
-            if (!dT[i]) continue;
-            if (!X[i] && p->sched.probs[(size_t)i].N > 0) return fail(TT_EINVAL, "X pointer is NULL");
-            if ((rc = coefficient_grads(d[i], n[i], T[i], dB[i], X[i], dT[i], dense_grad, W, st))) return rc;
-        }
+        if (!X) return fail(TT_EINVAL, "X is needed for the coefficient gradients");
+        if ((rc = grads_batched(p, T, X, (const double* const*)dB, dT, dense_grad, st))) return rc;
     }
     return tt_plan_status(p);
 }

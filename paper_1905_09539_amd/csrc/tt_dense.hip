@@ -4,9 +4,10 @@
 //                     (B x_mu U_mu^T before the solve, X x_mu U_mu after),
 //                     by the C_mu^{-1} reduction of the pair form and by the
 //                     FP64 residual of iterative refinement;
-//   gram_kernel     - split-K partial sums of P_(mu) Q_(mu)^T, the
-//                     coefficient gradient -Lam_(mu) X_(mu)^T of the adjoint;
-//   gram_reduce_kernel, axpy, norms and precision conversions.
+//   gram_batched_kernel - split-K partial sums of P_(mu) Q_(mu)^T for a table
+//                     of (problem, mode) jobs: the coefficient gradients
+//                     -Lam_(mu) X_(mu)^T of the adjoint;
+//   gram_reduce_batched_kernel, axpy, norms and precision conversions.
 //
 // A tensor of shape (n_1..n_d) in C order is viewed, for mode mu, as
 // [L][n_mu][R] with L = prod_{nu<mu} n_nu and R = prod_{nu>mu} n_nu.
@@ -20,6 +21,7 @@ constexpr int kDT = 64;      // output tile edge
 constexpr int kDKC = 16;     // K chunk staged through LDS
 constexpr int kDRow = 80;    // LDS row pitch (doubles)
 constexpr int kDThreads = 256;
+static_assert(kDT == kGramTile && kDKC == kGramKC, "Gram job planning assumes the kernel's tile and K chunk");
 
 // 2x2 blocks of 16x16x4 MFMA per wave over one K chunk.  LP = false:
 // v_mfma_f64_16x16x4f64; LP = true: operands rounded to FP32 and
@@ -224,20 +226,16 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
 // ---------------------------------------------------------------------------
 // Split-K Gram product of two tensors of the same shape [L][n][R]:
 //   W[s][a][b] = sum_{k in chunk s} P[a, k] Q[b, k],  k = l R + r,
-// P[a, k] = P[l n R + a R + r].  One workgroup per (a tile, b tile, chunk).
+// P[a, k] = P[l n R + a R + r].  One workgroup per (a tile, b tile, chunk);
+// the batched kernel maps its workgroups to jobs through their wg_first.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kDThreads) void gram_kernel(const double* __restrict__ P,
-                                                         const double* __restrict__ Q,
-                                                         double* __restrict__ W, int n, int64_t L,
-                                                         int64_t R, int64_t kchunk) {
+__device__ inline void gram_block(const double* __restrict__ P, const double* __restrict__ Q,
+                                  double* __restrict__ W, int n, int64_t L, int64_t R, int64_t kchunk, int a0,
+                                  int b0, int s) {
     __shared__ double As[kDKC * kDRow];
     __shared__ double Bs[kDKC * kDRow];
     __shared__ int64_t kOff[kDKC];
     const int tid = threadIdx.x;
-    const int nt = (n + kDT - 1) / kDT;
-    const int a0 = (blockIdx.x % nt) * kDT;
-    const int b0 = (blockIdx.x / nt) * kDT;
-    const int s = blockIdx.y;
     const int64_t K = L * R;
     const int64_t kbeg = (int64_t)s * kchunk;
     const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
@@ -320,20 +318,40 @@ __global__ __launch_bounds__(kDThreads) void gram_kernel(const double* __restric
         }
 }
 
-// out[a][b] = scale * sum_s W[s][a][b], masked to the quasi-triangular pattern
-// of T (a <= b, or a == b + 1 with T[a][b] != 0) unless dense != 0.
-__global__ void gram_reduce_kernel(const double* __restrict__ W, int nsplit, int n,
-                                   const double* __restrict__ T, int dense, double scale,
-                                   double* __restrict__ out) {
-    const int64_t nn = (int64_t)n * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int a = (int)(e / n), b = (int)(e - (e / n) * n);
-        bool keep = dense || a <= b || (a == b + 1 && T[e] != 0.0);
+// the last job whose range starts at or before idx (ranges ascending)
+template <bool EL>
+__device__ inline int gram_job_of(const GramJob* __restrict__ jobs, int njobs, int64_t idx) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((EL ? jobs[mid].el_first : jobs[mid].wg_first) <= idx)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kDThreads) void gram_batched_kernel(const GramJob* __restrict__ jobs, int njobs) {
+    const GramJob& J = jobs[gram_job_of<false>(jobs, njobs, blockIdx.x)];
+    const int64_t b = (int64_t)blockIdx.x - J.wg_first;
+    const int nt = (J.n + kDT - 1) / kDT;
+    const int tile = (int)(b % (nt * nt)), s = (int)(b / (nt * nt));
+    gram_block(J.P, J.Q, J.W, J.n, J.L, J.R, J.kchunk, (tile % nt) * kDT, (tile / nt) * kDT, s);
+}
+
+__global__ void gram_reduce_batched_kernel(const GramJob* __restrict__ jobs, int njobs, int64_t elems,
+                                           double scale) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < elems;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const GramJob& J = jobs[gram_job_of<true>(jobs, njobs, g)];
+        const int64_t e = g - J.el_first, nn = (int64_t)J.n * J.n;
+        const int a = (int)(e / J.n), b = (int)(e - (e / J.n) * J.n);
+        const bool keep = J.dense || a <= b || (a == b + 1 && J.T[e] != 0.0);
         double acc = 0.0;
         if (keep)
-            for (int s = 0; s < nsplit; ++s) acc += W[(int64_t)s * nn + e];
-        out[e] = keep ? scale * acc : 0.0;
+            for (int s = 0; s < J.nsplit; ++s) acc += J.W[(int64_t)s * nn + e];
+        J.out[e] = keep ? scale * acc : 0.0;
     }
 }
 
@@ -404,33 +422,12 @@ hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const do
     return hipGetLastError();
 }
 
-int gram_splits(int n, int64_t K) {
-    const int nt = (n + kDT - 1) / kDT;
-    int64_t want = 2048 / (nt * nt);
-    int64_t maxs = K / 512;
-    if (want > maxs) want = maxs;
-    if (want < 1) want = 1;
-    if (want > 1024) want = 1024;
-    return (int)want;
-}
-
-hipError_t launch_gram(const double* P, const double* Q, double* W, int nsplit, int n, int64_t L, int64_t R,
-                       hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    const int nt = (n + kDT - 1) / kDT;
-    const int64_t K = L * R;
-    int64_t kchunk = (K + nsplit - 1) / nsplit;
-    kchunk = (kchunk + kDKC - 1) / kDKC * kDKC;
-    hipLaunchKernelGGL(gram_kernel, dim3((unsigned)(nt * nt), (unsigned)nsplit), dim3(kDThreads), 0, st, P, Q, W,
-                       n, L, R, kchunk);
-    return hipGetLastError();
-}
-
-hipError_t launch_gram_reduce(const double* W, int nsplit, int n, const double* T, int dense, double scale,
-                              double* out, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(gram_reduce_kernel, dim3(elem_grid((int64_t)n * n)), dim3(256), 0, st, W, nsplit, n, T,
-                       dense, scale, out);
+hipError_t launch_gram_batched(const GramJob* jobs, int njobs, int64_t wgs, int64_t elems, double scale,
+                               hipStream_t st) {
+    if (njobs <= 0 || wgs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gram_batched_kernel, dim3((unsigned)wgs), dim3(kDThreads), 0, st, jobs, njobs);
+    hipLaunchKernelGGL(gram_reduce_batched_kernel, dim3(elem_grid(elems)), dim3(256), 0, st, jobs, njobs, elems,
+                       scale);
     return hipGetLastError();
 }
 

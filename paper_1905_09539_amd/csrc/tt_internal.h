@@ -156,13 +156,22 @@ hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st
 // Y = alpha (X x_mu M) + beta Z with M row-major nout x nin; Z may be Y.
 hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
                            int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st);
-// Split-K Gram product W[s] = P_(mu) Q_(mu)^T over K chunk s, then
-// out = scale * sum_s W[s] masked to the pattern of T unless dense.
-int gram_splits(int n, int64_t K);
-hipError_t launch_gram(const double* P, const double* Q, double* W, int nsplit, int n, int64_t L, int64_t R,
-                       hipStream_t st);
-hipError_t launch_gram_reduce(const double* W, int nsplit, int n, const double* T, int dense, double scale,
-                              double* out, hipStream_t st);
+// Several Gram products in two launches (one split-K Gram pass over all jobs,
+// one reduce pass): job j owns workgroups [wg_first, wg_first + nt^2 nsplit)
+// and output elements [el_first, el_first + n^2).
+constexpr int kGramTile = 64;  // output tile edge of the Gram kernels
+constexpr int kGramKC = 16;    // their K chunk
+struct GramJob {
+    const double* P;
+    const double* Q;
+    double* W;
+    const double* T;
+    double* out;
+    int64_t L, R, kchunk, wg_first, el_first;
+    int n, nsplit, dense, pad;
+};
+hipError_t launch_gram_batched(const GramJob* jobs, int njobs, int64_t wgs, int64_t elems, double scale,
+                               hipStream_t st);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
 int sumsq_blocks();
 hipError_t launch_sumsq2(const double* x, const double* y, int64_t n, double* part, hipStream_t st);
