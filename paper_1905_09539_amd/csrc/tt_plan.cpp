@@ -315,7 +315,27 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             return TT_EINVAL;
         }
 
+    // Per (problem, mode, block): tuples, 1x1 tuples and 2x2 blocks.
+    struct BlockInfo {
+        int tuples, ones, bumps;
+    };
+    std::vector<std::vector<std::vector<BlockInfo>>> binfo(s.probs.size());
+    for (size_t pi = 0; pi < s.probs.size(); ++pi) {
+        const HostProblem& p = s.probs[pi];
+        binfo[pi].resize((size_t)D);
+        for (int mu = 0; mu < D; ++mu)
+            for (int b = 0; b < p.m[mu]; ++b) {
+                const int64_t r0 = p.bst[mu][b], r1 = p.bst[mu][b + 1], nm = p.n[mu];
+                BlockInfo bi{};
+                bi.tuples = tuple_count(p.T[mu], nm, r0, r1, &bi.ones);
+                for (int64_t i = r0; i + 1 < r1; ++i)
+                    if (p.T[mu][(size_t)((i + 1) * nm + i)] != 0.0) ++bi.bumps;
+                binfo[pi][(size_t)mu].push_back(bi);
+            }
+    }
+
     // Leaf flags: accumulator reads and the adjacent block.
+    std::vector<int32_t> order;
     for (int64_t w = 0; w < W; ++w) {
         Wave wv;
         wv.leaf_first = (int64_t)s.leaves.size();
@@ -329,10 +349,10 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             for (int mu = 0; mu < D; ++mu) {
                 if (mu > 0 && received[(size_t)L.prob][(size_t)(block_lin(p, I) * D + mu)]) L.flags |= 1 << mu;
                 if (I[mu] + 1 < p.m[mu]) L.flags |= 1 << (4 + mu);
-                int ones = 0;
-                tm[mu] = tuple_count(p.T[mu], p.n[mu], p.bst[mu][I[mu]], p.bst[mu][I[mu] + 1], &ones);
-                all *= tm[mu];
-                single *= ones;
+                const BlockInfo& bi = binfo[(size_t)L.prob][(size_t)mu][(size_t)I[mu]];
+                tm[mu] = bi.tuples;
+                all *= bi.tuples;
+                single *= bi.ones;
             }
             s.maxcpl = std::max(s.maxcpl, all - single);
             L.shape = shape_index(s, known_shapes, tm);
@@ -345,10 +365,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             }
             double lf = 0, lb = 16.0 * (double)ne;
             for (int mu = 0; mu < D; ++mu) {
-                int64_t st = p.bst[mu][I[mu]], nm = p.n[mu];
-                int64_t bumps = 0;
-                for (int64_t i = st; i + 1 < st + sz[mu]; ++i)
-                    if (p.T[mu][(i + 1) * nm + i] != 0.0) ++bumps;
+                const int64_t bumps = binfo[(size_t)L.prob][(size_t)mu][(size_t)I[mu]].bumps;
                 double off = (double)sz[mu] * (double)(sz[mu] - 1) / 2.0 + (double)bumps;
                 lf += 2.0 * off * (double)(ne / sz[mu]);
                 lb += 8.0 * (double)(sz[mu] * sz[mu]);
@@ -367,7 +384,14 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
         // update tiles triggered by the previous wave
         wv.item_first = (int64_t)s.items.size();
         if (w >= 1) {
-            for (int32_t tid : triggered[(size_t)(w - 1)]) {
+            // longest tiles first (the work of a tile grows with K), so that
+            // the launch does not end on a few long tiles; tiles of one task
+            // stay adjacent
+            order = triggered[(size_t)(w - 1)];
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                return s.tasks[(size_t)a].K > s.tasks[(size_t)b].K;
+            });
+            for (int32_t tid : order) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
                 const bool right = (t.mode == D - 1);
                 int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
@@ -386,12 +410,6 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             }
         }
         wv.item_count = (int64_t)s.items.size() - wv.item_first;
-        // longest tiles first (the work of a tile grows with K), so that the
-        // launch does not end on a few long tiles; tiles of one task stay
-        // adjacent
-        std::stable_sort(s.items.begin() + wv.item_first, s.items.end(), [&](const WorkItem& a, const WorkItem& b) {
-            return s.tasks[(size_t)a.task].K > s.tasks[(size_t)b.task].K;
-        });
         s.waves.push_back(wv);
     }
     if (!triggered[(size_t)(W > 0 ? W - 1 : 0)].empty()) {
