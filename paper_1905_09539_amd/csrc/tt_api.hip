@@ -1185,7 +1185,10 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
     int64_t total = 1;
     for (int mu = 0; mu < D; ++mu) total *= hp.m[mu];
     std::vector<int> solved((size_t)total, 0);
+    // per (block, mode): delivered source blocks, their index sum and
+    // square sum (a source delivered twice and another never is caught)
     std::vector<int> pending((size_t)total * D, 0);
+    std::vector<int64_t> psum((size_t)total * D, 0), psq((size_t)total * D, 0);
     auto lin = [&](const int* I) {
         int64_t l = 0;
         for (int mu = 0; mu < D; ++mu) l = l * hp.m[mu] + I[mu];
@@ -1205,7 +1208,11 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
     for (size_t k = 0; k < s.waves.size(); ++k) {
         const Wave& wv = s.waves[k];
         int64_t last_task = -1;
-        std::vector<std::pair<int64_t, int>> deliveries;
+        struct Delivery {
+            int64_t at;
+            int slo, shi;
+        };
+        std::vector<Delivery> deliveries;
         for (int64_t q = 0; q < wv.item_count; ++q) {
             const WorkItem& w = s.items[(size_t)(wv.item_first + q)];
             if (w.task == last_task) continue;
@@ -1232,7 +1239,7 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
             for (int b = lo; b < hi_t; ++b) {
                 I[mu] = b;
                 if (solved[(size_t)lin(I)] || wave_of(I) <= (int64_t)k) bad = 1;
-                deliveries.push_back({lin(I) * D + mu, shi - slo});
+                deliveries.push_back({lin(I) * D + mu, slo, shi});
             }
         }
         if (bad) break;
@@ -1250,7 +1257,14 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
                 }
                 const int adj = (I[mu] + 1 < hp.m[mu]) ? 1 : 0;
                 if (((lf.flags >> (4 + mu)) & 1) != adj) bad = 1;
-                if (pending[(size_t)lin(I) * D + mu] + adj != hp.m[mu] - 1 - I[mu]) bad = 1;
+                const size_t at = (size_t)lin(I) * D + mu;
+                if (pending[at] + adj != hp.m[mu] - 1 - I[mu]) bad = 1;
+                int64_t es = 0, eq = 0;  // sources I+2 .. m-1
+                for (int64_t b = I[mu] + 2; b < hp.m[mu]; ++b) {
+                    es += b;
+                    eq += b * b;
+                }
+                if (psum[at] != es || psq[at] != eq) bad = 1;
                 if (mu >= 1 && (((lf.flags >> mu) & 1) != (pending[(size_t)lin(I) * D + mu] > 0 ? 1 : 0))) bad = 1;
             }
         }
@@ -1261,7 +1275,13 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
             solved[(size_t)lin(I)] = 1;
         }
         // the updates of this wave complete before the next wave
-        for (auto& dv : deliveries) pending[(size_t)dv.first] += dv.second;
+        for (const Delivery& dv : deliveries) {
+            pending[(size_t)dv.at] += dv.shi - dv.slo;
+            for (int64_t b = dv.slo; b < dv.shi; ++b) {
+                psum[(size_t)dv.at] += b;
+                psq[(size_t)dv.at] += b * b;
+            }
+        }
     }
     for (int64_t k = 0; k < total; ++k)
         if (!solved[(size_t)k]) bad = 1;

@@ -287,6 +287,12 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
     //   (1) targets [c-s, c-1) from sources [c, c+s), ready once c is solved;
     //   (2) target  c-1        from sources [c+1, c+s), ready once c+1 is.
     // Both have at least one hyperplane of slack before their targets run.
+    // With m = 2^L + 1 blocks (a partition pushed one block past a power of
+    // two by the 2x2 blocks) the splits run over 2^L blocks whose last one is
+    // the pair {m-2, m-1}: every update whose sources end at block m-2 also
+    // takes block m-1, block m-3 receives block m-1 in a task of its own, and
+    // the lone split at c = m-1 (a rank-|block| update of every other block,
+    // a whole pass over the tensor) disappears.
     for (int64_t w = 0; w < W; ++w) {
         for (const LeafDesc& L0 : waves[(size_t)w]) {
             const HostProblem& p = s.probs[(size_t)L0.prob];
@@ -294,17 +300,24 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             for (int mu = 0; mu < D; ++mu) I[mu] = L0.blk[mu];
             for (int mu = 0; mu < D; ++mu) {
                 const int m = p.m[mu];
+                const bool fold = m >= 5 && ((m - 1) & (m - 2)) == 0;
+                const int mt = fold ? m - 1 : m;  // blocks of the split tree
                 const int c = I[mu];
+                auto src_end = [&](int e) { return (fold && e >= mt) ? m : std::min(e, m); };
+                if (fold && c == m - 1) {  // block m-3 from block m-1
+                    add_task(p, L0.prob, I, mu, m - 3, m - 2, m - 1, m, w);
+                    continue;
+                }
                 // type (1): this block is the midpoint c
                 if (c >= 1) {
                     const int sb = lowbit(c);
-                    if (sb >= 2) add_task(p, L0.prob, I, mu, c - sb, c - 1, c, std::min(c + sb, m), w);
+                    if (sb >= 2) add_task(p, L0.prob, I, mu, c - sb, c - 1, c, src_end(c + sb), w);
                 }
                 // type (2): this block is c + 1 for the midpoint c = I - 1
                 const int c2 = c - 1;
                 if (c2 >= 1) {
                     const int sb = lowbit(c2);
-                    if (sb >= 2) add_task(p, L0.prob, I, mu, c2 - 1, c2, c2 + 1, std::min(c2 + sb, m), w);
+                    if (sb >= 2) add_task(p, L0.prob, I, mu, c2 - 1, c2, c2 + 1, src_end(c2 + sb), w);
                 }
             }
         }
