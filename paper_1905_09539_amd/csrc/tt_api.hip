@@ -313,6 +313,7 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
     TT_HIP_CHECK(hipEventRecord(P->ev_start, st));
     TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->ev_start, 0));
     const size_t W = s.waves.size();
+    const int leaf_lds = leaf_lds_bytes(s.D, s.bmax, s.maxtup, s.maxcpl, s.maxH);
     for (size_t k = 0; k < W; ++k) {
         const Wave& wv = s.waves[k];
         if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(st, P->evU[k - 1], 0));
@@ -327,7 +328,8 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
         hipStream_t us = serial ? st : P->side;
         if (k >= 1 && !serial) TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->evL[k - 1], 0));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ub[k], us));
-        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp, us));
+        TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp,
+                                   leaf_lds, us));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->ua[k], us));
         TT_HIP_CHECK(hipEventRecord(P->evU[k], us));
     }

@@ -229,8 +229,8 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
 // P[a, k] = P[l n R + a R + r].  One workgroup per (a tile, b tile, chunk);
 // the batched kernel maps its workgroups to jobs through their wg_first.
 // ---------------------------------------------------------------------------
-__device__ inline void gram_block(const double* __restrict__ P, const double* __restrict__ Q,
-                                  double* __restrict__ W, int n, int64_t L, int64_t R, int64_t kchunk, int a0,
+__device__ inline void gram_block(const gdouble* __restrict__ P, const gdouble* __restrict__ Q,
+                                  gdouble* __restrict__ W, int n, int64_t L, int64_t R, int64_t kchunk, int a0,
                                   int b0, int s) {
     __shared__ double As[kDKC * kDRow];
     __shared__ double Bs[kDKC * kDRow];
@@ -254,8 +254,8 @@ __device__ inline void gram_block(const double* __restrict__ P, const double* __
         // thread: row a = tid / 4 (of both tiles), 4 consecutive k
         const int ar = tid >> 2, ak = (tid & 3) * 4;
         const bool pa = (a0 + ar) < n, qb = (b0 + ar) < n;
-        const double* Pr = P + (int64_t)(a0 + ar) * R;
-        const double* Qr = Q + (int64_t)(b0 + ar) * R;
+        const gdouble* Pr = P + (int64_t)(a0 + ar) * R;
+        const gdouble* Qr = Q + (int64_t)(b0 + ar) * R;
         double ra[4], rb[4];
         for (int64_t kc = kbeg; kc < kend; kc += kDKC) {
             __syncthreads();
@@ -286,8 +286,8 @@ __device__ inline void gram_block(const double* __restrict__ P, const double* __
         for (int64_t kc = kbeg; kc < kend; kc += kDKC) {
             const int64_t k = kc + kk;
             const bool kv = k < kend;
-            const double* Pr = P + k * n;
-            const double* Qr = Q + k * n;
+            const gdouble* Pr = P + k * n;
+            const gdouble* Qr = Q + k * n;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 ra[i] = (kv && a0 + ac + i < n) ? Pr[a0 + ac + i] : 0.0;
@@ -303,7 +303,7 @@ __device__ inline void gram_block(const double* __restrict__ P, const double* __
             mfma_chunk16<false>(As, Bs, wr, wc, li, lk, acc);
         }
     }
-    double* Ws = W + (int64_t)s * n * n;
+    gdouble* Ws = W + (int64_t)s * n * n;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kDThreads) void gram_batched_kernel(const GramJob* 
     const int64_t b = (int64_t)blockIdx.x - J.wg_first;
     const int nt = (J.n + kDT - 1) / kDT;
     const int tile = (int)(b % (nt * nt)), s = (int)(b / (nt * nt));
-    gram_block(J.P, J.Q, J.W, J.n, J.L, J.R, J.kchunk, (tile % nt) * kDT, (tile / nt) * kDT, s);
+    gram_block(to_global(J.P), to_global(J.Q), to_global(J.W), J.n, J.L, J.R, J.kchunk, (tile % nt) * kDT, (tile / nt) * kDT, s);
 }
 
 __global__ void gram_reduce_batched_kernel(const GramJob* __restrict__ jobs, int njobs, int64_t elems,
@@ -347,11 +347,12 @@ __global__ void gram_reduce_batched_kernel(const GramJob* __restrict__ jobs, int
         const GramJob& J = jobs[gram_job_of<true>(jobs, njobs, g)];
         const int64_t e = g - J.el_first, nn = (int64_t)J.n * J.n;
         const int a = (int)(e / J.n), b = (int)(e - (e / J.n) * J.n);
-        const bool keep = J.dense || a <= b || (a == b + 1 && J.T[e] != 0.0);
+        const bool keep = J.dense || a <= b || (a == b + 1 && to_global(J.T)[e] != 0.0);
+        const gdouble* W = to_global(J.W);
         double acc = 0.0;
         if (keep)
-            for (int s = 0; s < J.nsplit; ++s) acc += J.W[(int64_t)s * nn + e];
-        J.out[e] = keep ? scale * acc : 0.0;
+            for (int s = 0; s < J.nsplit; ++s) acc += W[(int64_t)s * nn + e];
+        to_global(J.out)[e] = keep ? scale * acc : 0.0;
     }
 }
 

@@ -18,6 +18,17 @@ constexpr int kMaxLeaf = 24;      // largest leaf block edge
 constexpr int kUpdThreads = 256;  // one workgroup per 64x64 update tile
 constexpr int kTile = 64;
 
+// Global-memory views of the pointers the kernels read from device tables.
+// A pointer loaded from memory is generic to the compiler, which then emits
+// flat loads and stores; a flat access counts against the LDS counter as
+// well, so every wait for an LDS result would also wait for all memory loads
+// in flight (no prefetch survives an LDS read).
+typedef __attribute__((address_space(1))) double gdouble;
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* to_global(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Per-problem description as the kernels see it (device table).
 struct ProbDesc {
     double* X;                   // solution / right-hand side, in place
@@ -147,8 +158,10 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
 hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
                        const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
                        const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st);
+// leaf_lds: LDS bytes of a leaf workgroup that should fit on a CU beside two
+// update workgroups (0: no limit on update workgroups per CU)
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
-                         int64_t count, const ProbDesc* probs, int lp, hipStream_t st);
+                         int64_t count, const ProbDesc* probs, int lp, int leaf_lds, hipStream_t st);
 hipError_t launch_zero_int(int* p, int count, hipStream_t st);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st);
 

@@ -30,6 +30,17 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kKC = 16;      // K chunk
 constexpr int kLdsRow = 80;  // 64 + 16 doubles: rows k and k+1 use disjoint bank halves
 
+// Operand loads of the update kernel are never skipped: a lane whose element
+// lies outside the tile reads this zero instead.  A masked load (select after
+// a load) is turned back into a branch around the load by the compiler, with
+// a wait for the load inside the branch; a load from a selected address stays
+// unconditional, so the loads of the next chunks remain in flight.
+__device__ double kZeroOperand[2];
+
+__device__ inline const gdouble* pick(bool valid, const gdouble* p) {
+    return valid ? p : (const gdouble*)to_global(&kZeroOperand[0]);
+}
+
 __device__ inline int64_t pencil_col_offset(const UpdDesc& t, int c) {
     int64_t off = t.xbase;
     int rem = c;
@@ -88,8 +99,8 @@ __device__ inline void mfma_chunk(const double* As, const double* Bs, int wr, in
 // wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
 // the target rows; right path (fastest mode): MFMA rows are pencil columns.
 template <bool LP>
-__device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const double* __restrict__ X,
-                                double* __restrict__ C, const double* __restrict__ T, int64_t nmu, int64_t smu,
+__device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
+                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
                                 bool right, bool store, double sgn, double* As, double* Bs, int64_t* colOff) {
     constexpr int kW = 4 * kTile;  // 256 pencil columns
     constexpr int kWRow = kW + 16;  // LDS row pitch of the 256-wide operand
@@ -111,19 +122,19 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const doub
     // pencil column (8 values along K) per thread
     const int tr = (tid >> 3) & 15, tk = tid & 7;
     const bool tval = tid < 128 && tr < t.M;
-    const double* Trow = T + (int64_t)(t.r0 + tr) * nmu + t.k0;
+    const gdouble* Trow = T + (int64_t)(t.r0 + tr) * nmu + t.k0;
     const bool cval = (col0 + tid) < t.P;
     const int64_t coff = colOff[tid];
     double ra, rb[kKW];
     auto gload = [&](int kc) {
-        ra = (tval && kc + tk < t.K) ? Trow[kc + tk] : 0.0;
+        ra = *pick(tval && kc + tk < t.K, Trow + kc + tk);
         if (!right) {
 #pragma unroll
             for (int k = 0; k < kKW; ++k)
-                rb[k] = (cval && kc + k < t.K) ? X[coff + (int64_t)(t.k0 + kc + k) * smu] : 0.0;
+                rb[k] = *pick(cval && kc + k < t.K, X + coff + (int64_t)(t.k0 + kc + k) * smu);
         } else {
 #pragma unroll
-            for (int k = 0; k < kKW; ++k) rb[k] = (cval && kc + k < t.K) ? X[coff + t.k0 + kc + k] : 0.0;
+            for (int k = 0; k < kKW; ++k) rb[k] = *pick(cval && kc + k < t.K, X + coff + t.k0 + kc + k);
         }
     };
     gload(0);
@@ -160,10 +171,42 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const doub
             const int c = wave * 64 + b * 16 + (right ? i : li);
             const int r = right ? li : i;
             if (col0 + c >= t.P || r >= t.M) continue;
-            double* p = C + colOff[c] + (int64_t)(t.r0 + r) * smu;
+            gdouble* p = C + colOff[c] + (int64_t)(t.r0 + r) * smu;
             const double val = sgn * (double)acc[b][v];
             *p = store ? val : *p + val;
         }
+}
+
+// K loop over nchunk chunks with two register sets of operands in flight:
+// chunk c is computed while chunks c+1 and c+2 load.  load(set, k) fills a
+// set from K offset k, stage(set) moves it to LDS, compute() consumes LDS.
+// The steady state has no conditional load, so the wait before each stage
+// leaves the other set's loads outstanding; the last one to three chunks
+// are peeled.
+template <class Load, class Stage, class Compute>
+__device__ inline void k_pipeline(int nchunk, Load&& load, Stage&& stage, Compute&& compute) {
+    load(0, 0);
+    load(1, min(1, nchunk - 1) * kKC);  // a repeated chunk 0 when nchunk == 1
+    int ch = 0;
+    for (; ch + 3 < nchunk; ch += 2) {
+        stage(0);
+        load(0, (ch + 2) * kKC);
+        compute();
+        stage(1);
+        load(1, (ch + 3) * kKC);
+        compute();
+    }
+    stage(0);
+    if (ch + 2 < nchunk) load(0, (ch + 2) * kKC);
+    compute();
+    if (ch + 1 < nchunk) {
+        stage(1);
+        compute();
+    }
+    if (ch + 2 < nchunk) {
+        stage(0);
+        compute();
+    }
 }
 
 template <bool LP>
@@ -182,9 +225,9 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
     const UpdDesc t = tasks[wi.task];
     const ProbDesc& P = probs[t.prob];
     const int mode = t.mode;
-    const double* __restrict__ X = P.X;
-    double* __restrict__ C = (mode == 0) ? P.X : P.A[mode];
-    const double* __restrict__ T = P.T[mode];
+    const gdouble* __restrict__ X = to_global(P.X);
+    gdouble* __restrict__ C = to_global((mode == 0) ? P.X : P.A[mode]);
+    const gdouble* __restrict__ T = to_global(P.T[mode]);
     const int64_t nmu = P.n[mode];
     const int64_t smu = P.stride[mode];
     const bool right = (mode == D - 1);
@@ -227,18 +270,18 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             bval[i] = (col0 + lb_c + i) < t.P;
         }
         const bool aval_r = (row0 + la_r) < t.M;
-        const double* Arow = T + (int64_t)(t.r0 + row0 + la_r) * nmu + t.k0;
+        const gdouble* Arow = T + (int64_t)(t.r0 + row0 + la_r) * nmu + t.k0;
         auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                int k = kc + la_k + i;
-                ra[i] = (aval_r && k < t.K) ? Arow[k] : 0.0;
+                const int k = kc + la_k + i;
+                ra[i] = *pick(aval_r && k < t.K, Arow + k);
             }
-            int kb = kc + lb_k;
-            bool kvalid = kb < t.K;
-            int64_t roff = (int64_t)(t.k0 + kb) * smu;
+            const int kb = kc + lb_k;
+            const bool kvalid = kb < t.K;
+            const int64_t roff = (int64_t)(t.k0 + kb) * smu;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) rb[i] = (kvalid && bval[i]) ? X[boff[i] + roff] : 0.0;
+            for (int i = 0; i < 4; ++i) rb[i] = *pick(kvalid && bval[i], X + boff[i] + roff);
         };
         auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
             __syncthreads();
@@ -248,18 +291,10 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             for (int i = 0; i < 4; ++i) Bs[lb_k * kLdsRow + lb_c + i] = rb[i];
             __syncthreads();
         };
-        // chunk c is computed while chunks c+1 and c+2 are in flight
-        gload(ra0, rb0, 0);
-        if (nchunk > 1) gload(ra1, rb1, kKC);
-        for (int ch = 0; ch < nchunk; ch += 2) {
-            stage(ra0, rb0);
-            if (ch + 2 < nchunk) gload(ra0, rb0, (ch + 2) * kKC);
-            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
-            if (ch + 1 >= nchunk) break;
-            stage(ra1, rb1);
-            if (ch + 3 < nchunk) gload(ra1, rb1, (ch + 3) * kKC);
-            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
-        }
+        k_pipeline(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() { mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc); });
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int c = wc + 16 * j + li;
@@ -271,7 +306,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                 for (int v = 0; v < 4; ++v) {
                     const int r = wr + 16 * i + mfma_row<LP>(v, lk);
                     if (row0 + r < t.M) {
-                        double* p = C + coff + (int64_t)(t.r0 + row0 + r) * smu;
+                        gdouble* p = C + coff + (int64_t)(t.r0 + row0 + r) * smu;
                         const double val = sgn * (double)acc[i][j][v];
                         *p = store ? val : *p + val;
                     }
@@ -282,15 +317,15 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
         const int lr = tid >> 2, lk4 = (tid & 3) * 4;
         const bool cval = (col0 + lr) < t.P;
         const bool rval = (row0 + lr) < t.M;
-        const double* Xrow = X + colOff[lr] + t.k0;
-        const double* Trow = T + (int64_t)(t.r0 + row0 + lr) * nmu + t.k0;
+        const gdouble* Xrow = X + colOff[lr] + t.k0;
+        const gdouble* Trow = T + (int64_t)(t.r0 + row0 + lr) * nmu + t.k0;
         double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
         auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                int k = kc + lk4 + i;
-                ra[i] = (cval && k < t.K) ? Xrow[k] : 0.0;
-                rb[i] = (rval && k < t.K) ? Trow[k] : 0.0;
+                const int k = kc + lk4 + i;
+                ra[i] = *pick(cval && k < t.K, Xrow + k);
+                rb[i] = *pick(rval && k < t.K, Trow + k);
             }
         };
         auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
@@ -302,17 +337,10 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
             }
             __syncthreads();
         };
-        gload(ra0, rb0, 0);
-        if (nchunk > 1) gload(ra1, rb1, kKC);
-        for (int ch = 0; ch < nchunk; ch += 2) {
-            stage(ra0, rb0);
-            if (ch + 2 < nchunk) gload(ra0, rb0, (ch + 2) * kKC);
-            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
-            if (ch + 1 >= nchunk) break;
-            stage(ra1, rb1);
-            if (ch + 3 < nchunk) gload(ra1, rb1, (ch + 3) * kKC);
-            mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc);
-        }
+        k_pipeline(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() { mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc); });
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -324,7 +352,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                 for (int j = 0; j < 2; ++j) {
                     const int r = wc + 16 * j + li;
                     if (row0 + r < t.M) {
-                        double* p = C + coff + t.r0 + row0 + r;
+                        gdouble* p = C + coff + t.r0 + row0 + r;
                         const double val = sgn * (double)acc[i][j][v];
                         *p = store ? val : *p + val;
                     }
@@ -348,13 +376,29 @@ __global__ void copy_kernel(const double* __restrict__ src, double* __restrict__
 // Launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,
-                         int64_t count, const ProbDesc* probs, int lp, hipStream_t st) {
+                         int64_t count, const ProbDesc* probs, int lp, int leaf_lds, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    // Unused LDS padding that holds the update to two workgroups per CU while
+    // a leaf workgroup (leaf_lds bytes) still fits beside them: with its
+    // registers alone three would fit, and leaves running concurrently would
+    // find no room on the CU.
+    size_t pad = 0;
+    if (leaf_lds > 0) {
+        int dev = 0, cu_lds = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess) {
+            constexpr int gran = 512;  // LDS allocation unit
+            constexpr int stat = (int)sizeof(double) * (2 * kKC * kLdsRow + 4 * kTile);  // the kernel's own
+            const int leaf = (leaf_lds + gran - 1) / gran * gran;
+            const int u = (cu_lds / 3 / gran + 1) * gran;  // the least of which three do not fit
+            if (2 * u + leaf <= cu_lds && u > stat && u <= 64 * 1024) pad = (size_t)(u - stat);
+        }
+    }
     if (lp)
-        hipLaunchKernelGGL(upd_kernel<true>, dim3((unsigned)count), dim3(kUpdThreads), 0, st, tasks, items, first,
+        hipLaunchKernelGGL(upd_kernel<true>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
                            probs, D);
     else
-        hipLaunchKernelGGL(upd_kernel<false>, dim3((unsigned)count), dim3(kUpdThreads), 0, st, tasks, items, first,
+        hipLaunchKernelGGL(upd_kernel<false>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
                            probs, D);
     return hipGetLastError();
 }

@@ -402,10 +402,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
         const int b = L.blk[mu];
-        r0[mu] = P.bst[mu][b];
-        const int r1 = P.bst[mu][b + 1];
+        const auto* bst = to_global(P.bst[mu]);
+        r0[mu] = bst[b];
+        const int r1 = bst[b + 1];
         sz[mu] = r1 - r0[mu];
-        nx[mu] = ((L.flags >> (4 + mu)) & 1) ? P.bst[mu][b + 2] - r1 : 0;
+        nx[mu] = ((L.flags >> (4 + mu)) & 1) ? bst[b + 2] - r1 : 0;
         gs[mu] = P.stride[mu];
         rsz[mu] = 1.0f / (float)sz[mu];
     }
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
     const LeafShape sh = shapes[L.shape];
     for (int i = tid; i <= sh.H; i += NT) hof[i] = hoffs[sh.hoff + i];
 
-    double* __restrict__ X = P.X;
+    gdouble* __restrict__ X = to_global(P.X);
     int64_t gbase = 0;
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) gbase += (int64_t)r0[mu] * gs[mu];
@@ -472,7 +473,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
 #pragma unroll
         for (int mu = 1; mu < D; ++mu) {
             if (!((L.flags >> mu) & 1)) continue;  // uniform
-            const double* __restrict__ A = P.A[mu];
+            const gdouble* __restrict__ A = to_global(P.A[mu]);
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u)
                 if (g[u] >= 0) v[u] -= A[g[u]];
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
     }
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) {
-        const double* T = P.T[mu];
+        const gdouble* T = to_global(P.T[mu]);
         const int64_t n = P.n[mu];
         const float rtp = 1.0f / (float)tp[mu];
         for (int e = tid; e < sz[mu] * tp[mu]; e += NT) {
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
     for (int mu = 0; mu < D; ++mu) {
         const int nxm = nx[mu];
         if (nxm == 0) continue;  // uniform over the workgroup
-        const double* T = P.T[mu];
+        const gdouble* T = to_global(P.T[mu]);
         const int64_t n = P.n[mu];
         const int r1 = r0[mu] + sz[mu];
         for (int e = tid; e < sz[mu] * nxm; e += NT) {
