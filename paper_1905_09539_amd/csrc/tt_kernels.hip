@@ -29,6 +29,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 constexpr int kKC = 16;      // K chunk
 constexpr int kLdsRow = 80;  // 64 + 16 doubles: rows k and k+1 use disjoint bank halves
+constexpr int kWideTDoubles = kKC * 17;                 // wide tile: 16 x 17 T block
+constexpr int kWideDoubles = kWideTDoubles + kKC * (4 * 64 + 16);  // plus 16 x 272 pencil block
+constexpr int kUpdSmemDoubles = (kWideDoubles > 2 * kKC * kLdsRow) ? kWideDoubles : 2 * kKC * kLdsRow;
 
 // Operand loads of the update kernel are never skipped: a lane whose element
 // lies outside the tile reads this zero instead.  A masked load (select after
@@ -70,15 +73,21 @@ __device__ inline int mfma_row(int v, int g) {
     return LP ? 4 * g + v : 4 * v + g;
 }
 
-template <bool LP>
-__device__ inline void mfma_chunk(const double* As, const double* Bs, int wr, int wc, int li, int lk,
-                                  typename MfmaAcc<LP>::type (&acc)[2][2]) {
+// One K chunk of a 64x64 tile: each wave's 32x32 block as 2x2 MFMA 16x16x4
+// blocks, operands from LDS.  An operand is staged either as [k][row] with
+// pitch kLdsRow or (ARK / BRK) as [row][k] with pitch kRkRow (odd, so the
+// sixteen rows a lane group reads fall in distinct banks).
+constexpr int kRkRow = kKC + 1;
+template <bool LP, bool ARK, bool BRK>
+__device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, int wc, int li, int lk,
+                                    typename MfmaAcc<LP>::type (&acc)[2][2]) {
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 4) {
-        const double* Ak = As + (kk + lk) * kLdsRow;
-        const double* Bk = Bs + (kk + lk) * kLdsRow;
-        double a0 = Ak[wr + li], a1 = Ak[wr + 16 + li];
-        double b0 = Bk[wc + li], b1 = Bk[wc + 16 + li];
+        const int k = kk + lk;
+        const double a0 = ARK ? As[(wr + li) * kRkRow + k] : As[k * kLdsRow + wr + li];
+        const double a1 = ARK ? As[(wr + 16 + li) * kRkRow + k] : As[k * kLdsRow + wr + 16 + li];
+        const double b0 = BRK ? Bs[(wc + li) * kRkRow + k] : Bs[k * kLdsRow + wc + li];
+        const double b1 = BRK ? Bs[(wc + 16 + li) * kRkRow + k] : Bs[k * kLdsRow + wc + 16 + li];
         if constexpr (LP) {
             const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
@@ -92,89 +101,6 @@ __device__ inline void mfma_chunk(const double* As, const double* Bs, int wr, in
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
     }
-}
-
-// Wide tile for updates with at most 16 target rows (the 64x64 tile would
-// leave 3/4 of its MFMA rows idle): 16 target rows x 256 pencil columns, each
-// wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
-// the target rows; right path (fastest mode): MFMA rows are pencil columns.
-template <bool LP>
-__device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
-                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
-                                bool right, bool store, double sgn, double* As, double* Bs, int64_t* colOff) {
-    constexpr int kW = 4 * kTile;  // 256 pencil columns
-    constexpr int kWRow = kW + 16;  // LDS row pitch of the 256-wide operand
-    constexpr int kKW = 8;         // K chunk of the wide tile
-    const int tid = threadIdx.x;
-    const int col0 = wi.ta * kW;
-    {
-        const int c = col0 + tid;
-        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
-    }
-    __syncthreads();
-    const int lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    typename MfmaAcc<LP>::type acc[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
-    const int nchunk = (t.K + kKW - 1) / kKW;
-    // loaders: the 16x8 T block (threads 0..127, one value each) and one
-    // pencil column (8 values along K) per thread
-    const int tr = (tid >> 3) & 15, tk = tid & 7;
-    const bool tval = tid < 128 && tr < t.M;
-    const gdouble* Trow = T + (int64_t)(t.r0 + tr) * nmu + t.k0;
-    const bool cval = (col0 + tid) < t.P;
-    const int64_t coff = colOff[tid];
-    double ra, rb[kKW];
-    auto gload = [&](int kc) {
-        ra = *pick(tval && kc + tk < t.K, Trow + kc + tk);
-        if (!right) {
-#pragma unroll
-            for (int k = 0; k < kKW; ++k)
-                rb[k] = *pick(cval && kc + k < t.K, X + coff + (int64_t)(t.k0 + kc + k) * smu);
-        } else {
-#pragma unroll
-            for (int k = 0; k < kKW; ++k) rb[k] = *pick(cval && kc + k < t.K, X + coff + t.k0 + kc + k);
-        }
-    };
-    gload(0);
-    for (int ch = 0; ch < nchunk; ++ch) {
-        __syncthreads();
-        if (tid < 128) As[tk * 16 + tr] = ra;  // T block as [k][r]
-#pragma unroll
-        for (int k = 0; k < kKW; ++k) Bs[k * kWRow + tid] = rb[k];  // pencil data as [k][c]
-        __syncthreads();
-        if (ch + 1 < nchunk) gload((ch + 1) * kKW);
-#pragma unroll
-        for (int kk = 0; kk < kKW; kk += 4) {
-            const double tv = As[(kk + lk) * 16 + li];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const double xv = Bs[(kk + lk) * kWRow + wave * 64 + b * 16 + li];
-                if constexpr (LP) {
-                    const float ft = (float)tv, fx = (float)xv;
-                    acc[b] = right ? __builtin_amdgcn_mfma_f32_16x16x4f32(fx, ft, acc[b], 0, 0, 0)
-                                   : __builtin_amdgcn_mfma_f32_16x16x4f32(ft, fx, acc[b], 0, 0, 0);
-                } else {
-                    acc[b] = right ? __builtin_amdgcn_mfma_f64_16x16x4f64(xv, tv, acc[b], 0, 0, 0)
-                                   : __builtin_amdgcn_mfma_f64_16x16x4f64(tv, xv, acc[b], 0, 0, 0);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            // left: D[r][c] with r = mfma row, c = lane column; right: D[c][r]
-            const int i = mfma_row<LP>(v, lk);
-            const int c = wave * 64 + b * 16 + (right ? i : li);
-            const int r = right ? li : i;
-            if (col0 + c >= t.P || r >= t.M) continue;
-            gdouble* p = C + colOff[c] + (int64_t)(t.r0 + r) * smu;
-            const double val = sgn * (double)acc[b][v];
-            *p = store ? val : *p + val;
-        }
 }
 
 // K loop over nchunk chunks with two register sets of operands in flight:
@@ -209,14 +135,125 @@ __device__ inline void k_pipeline(int nchunk, Load&& load, Stage&& stage, Comput
     }
 }
 
+// Wide tile for updates with at most 16 target rows (the 64x64 tile would
+// leave 3/4 of its MFMA rows idle): 16 target rows x 256 pencil columns, each
+// wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
+// the target rows; right path (fastest mode): MFMA rows are pencil columns.
 template <bool LP>
-__global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restrict__ tasks,
+__device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
+                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
+                                bool right, bool store, double sgn, double* As, double* Bs, int64_t* colOff) {
+    constexpr int kW = 4 * kTile;   // 256 pencil columns
+    constexpr int kWRow = kW + 16;  // LDS row pitch of the 256-wide operand
+    constexpr int kTRow = 17;       // LDS pitch of the 16x16 T block (odd: conflict-free staging)
+    const int tid = threadIdx.x;
+    const int col0 = wi.ta * kW;
+    {
+        const int c = col0 + tid;
+        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    typename MfmaAcc<LP>::type acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
+    const int nchunk = (t.K + kKC - 1) / kKC;
+    // loaders: one value of the 16x16 T block and one pencil column (16
+    // values along K) per thread
+    const int tr = tid >> 4, tk = tid & 15;
+    const bool tval = tr < t.M;
+    const gdouble* Trow = T + (int64_t)(t.r0 + tr) * nmu + t.k0;
+    const bool cval = (col0 + tid) < t.P;
+    const int64_t coff = colOff[tid];
+    // right path (fastest mode): the K run of a column is contiguous, so
+    // eight lanes share one column (two doubles each, one 128-byte line per
+    // eight lanes) and the block is staged as [c][k] with an odd pitch;
+    // thread tid takes columns j * 32 + tid / 8, K pair tid % 8
+    constexpr int kCRow = kKC + 1;
+    const int rk = 2 * (tid & 7);
+    double ra, rb[kKC];  // one chunk in flight
+    auto gload = [&](double& ra, double (&rb)[kKC], int kc) {
+        ra = *pick(tval && kc + tk < t.K, Trow + kc + tk);
+        if (!right) {
+#pragma unroll
+            for (int k = 0; k < kKC; ++k)
+                rb[k] = *pick(cval && kc + k < t.K, X + coff + (int64_t)(t.k0 + kc + k) * smu);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kKC / 2; ++j) {
+                const int c = j * 32 + (tid >> 3);
+                const bool cv = col0 + c < t.P;
+                const gdouble* xr = X + colOff[c] + t.k0 + kc + rk;
+                rb[2 * j] = *pick(cv && kc + rk < t.K, xr);
+                rb[2 * j + 1] = *pick(cv && kc + rk + 1 < t.K, xr + 1);
+            }
+        }
+    };
+    auto stage = [&](double ra, const double (&rb)[kKC]) {
+        __syncthreads();
+        As[tk * kTRow + tr] = ra;  // T block as [k][r]
+        if (!right) {
+#pragma unroll
+            for (int k = 0; k < kKC; ++k) Bs[k * kWRow + tid] = rb[k];  // pencil data as [k][c]
+        } else {
+#pragma unroll
+            for (int j = 0; j < kKC / 2; ++j) {  // pencil data as [c][k]
+                double* d = Bs + (j * 32 + (tid >> 3)) * kCRow + rk;
+                d[0] = rb[2 * j];
+                d[1] = rb[2 * j + 1];
+            }
+        }
+        __syncthreads();
+    };
+    auto compute = [&]() {
+#pragma unroll
+        for (int kk = 0; kk < kKC; kk += 4) {
+            const double tv = As[(kk + lk) * kTRow + li];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = wave * 64 + b * 16 + li;
+                const double xv = right ? Bs[c * kCRow + kk + lk] : Bs[(kk + lk) * kWRow + c];
+                if constexpr (LP) {
+                    const float ft = (float)tv, fx = (float)xv;
+                    acc[b] = right ? __builtin_amdgcn_mfma_f32_16x16x4f32(fx, ft, acc[b], 0, 0, 0)
+                                   : __builtin_amdgcn_mfma_f32_16x16x4f32(ft, fx, acc[b], 0, 0, 0);
+                } else {
+                    acc[b] = right ? __builtin_amdgcn_mfma_f64_16x16x4f64(xv, tv, acc[b], 0, 0, 0)
+                                   : __builtin_amdgcn_mfma_f64_16x16x4f64(tv, xv, acc[b], 0, 0, 0);
+                }
+            }
+        }
+    };
+    gload(ra, rb, 0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        stage(ra, rb);
+        if (ch + 1 < nchunk) gload(ra, rb, (ch + 1) * kKC);
+        compute();
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            // left: D[r][c] with r = mfma row, c = lane column; right: D[c][r]
+            const int i = mfma_row<LP>(v, lk);
+            const int c = wave * 64 + b * 16 + (right ? i : li);
+            const int r = right ? li : i;
+            if (col0 + c >= t.P || r >= t.M) continue;
+            gdouble* p = C + colOff[c] + (int64_t)(t.r0 + r) * smu;
+            const double val = sgn * (double)acc[b][v];
+            *p = store ? val : *p + val;
+        }
+}
+
+template <bool LP>
+__global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))) void upd_kernel(const UpdDesc* __restrict__ tasks,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t first,
                                                           const ProbDesc* __restrict__ probs, int D) {
     // one LDS buffer, carved per path: 64x64 tiles use two 16 x 80 operand
-    // blocks, wide tiles a 8 x 16 T block and a 8 x 272 pencil block
-    __shared__ double smem[2 * kKC * kLdsRow];
+    // blocks, wide tiles a 16 x 17 T block and a 16 x 272 pencil block
+    __shared__ double smem[kUpdSmemDoubles];
     __shared__ int64_t colOff[4 * kTile];
     double* As = smem;
     double* Bs = smem + kKC * kLdsRow;
@@ -234,7 +271,7 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
     const bool store = (t.flags & 1) != 0;
     const double sgn = (mode == 0) ? -1.0 : 1.0;
     if (t.M <= 16) {  // uniform over the workgroup
-        upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, sgn, smem, smem + 8 * 16, colOff);
+        upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, sgn, smem, smem + kWideTDoubles, colOff);
         return;
     }
     const int col0 = (right ? wi.ta : wi.tb) * kTile;  // pencil columns
@@ -258,43 +295,45 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
 
     if (!right) {
         // MFMA rows = target rows r, MFMA columns = pencil columns c.
-        // loaders: A: (row = tid/4, k = 4*(tid%4)..+3); B: (k = tid/16, c = 4*(tid%16)..+3)
-        const int la_r = tid >> 2, la_k = (tid & 3) * 4;
-        const int lb_k = tid >> 4, lb_c = (tid & 15) * 4;
+        // loaders: A (T rows, contiguous along K): rows tid/8 and 32 + tid/8,
+        // K pair tid%8, staged as [r][k]; B (pencil data): column tid%64 (one
+        // column per lane: consecutive lanes read consecutive memory within
+        // a pencil row), K rows 4*(tid/64)..+3
+        const int la_r = tid >> 3, la_k = 2 * (tid & 7);
+        const int lb_c = tid & 63, lb_k = (tid >> 6) * 4;
         double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
-        int64_t boff[4];
-        bool bval[4];
+        const bool bval = (col0 + lb_c) < t.P;
+        const gdouble* Bcol = X + colOff[lb_c] + (int64_t)(t.k0 + lb_k) * smu;
+        bool aval[2];
+        const gdouble* Arow[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            boff[i] = colOff[lb_c + i];
-            bval[i] = (col0 + lb_c + i) < t.P;
+        for (int j = 0; j < 2; ++j) {
+            aval[j] = (row0 + la_r + 32 * j) < t.M;
+            Arow[j] = T + (int64_t)(t.r0 + row0 + la_r + 32 * j) * nmu + t.k0 + la_k;
         }
-        const bool aval_r = (row0 + la_r) < t.M;
-        const gdouble* Arow = T + (int64_t)(t.r0 + row0 + la_r) * nmu + t.k0;
         auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = kc + la_k + i;
-                ra[i] = *pick(aval_r && k < t.K, Arow + k);
-            }
-            const int kb = kc + lb_k;
-            const bool kvalid = kb < t.K;
-            const int64_t roff = (int64_t)(t.k0 + kb) * smu;
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) rb[i] = *pick(kvalid && bval[i], X + boff[i] + roff);
+                for (int e = 0; e < 2; ++e) ra[2 * j + e] = *pick(aval[j] && kc + la_k + e < t.K, Arow[j] + kc + e);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                rb[i] = *pick(bval && kc + lb_k + i < t.K, Bcol + (int64_t)(kc + i) * smu);
         };
         auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 4; ++i) As[(la_k + i) * kLdsRow + la_r] = ra[i];
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) Bs[lb_k * kLdsRow + lb_c + i] = rb[i];
+                for (int e = 0; e < 2; ++e) As[(la_r + 32 * j) * kRkRow + la_k + e] = ra[2 * j + e];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Bs[(lb_k + i) * kLdsRow + lb_c] = rb[i];
             __syncthreads();
         };
         k_pipeline(
             nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
             [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
-            [&]() { mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc); });
+            [&]() { mfma_chunk_l<LP, true, false>(As, Bs, wr, wc, li, lk, acc); });
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int c = wc + 16 * j + li;
@@ -313,34 +352,49 @@ __global__ __launch_bounds__(kUpdThreads) void upd_kernel(const UpdDesc* __restr
                 }
         }
     } else {
-        // MFMA rows = pencil columns c, MFMA columns = target rows r.
-        const int lr = tid >> 2, lk4 = (tid & 3) * 4;
-        const bool cval = (col0 + lr) < t.P;
-        const bool rval = (row0 + lr) < t.M;
-        const gdouble* Xrow = X + colOff[lr] + t.k0;
-        const gdouble* Trow = T + (int64_t)(t.r0 + row0 + lr) * nmu + t.k0;
+        // MFMA rows = pencil columns c, MFMA columns = target rows r.  Both
+        // operands are contiguous along K: eight lanes share a row of either
+        // block (one 128-byte line per eight lanes) and the blocks are staged
+        // as [row][k] with an odd pitch.  Thread tid takes rows tid / 8 and
+        // 32 + tid / 8, K pair tid % 8.
+        const int lr = tid >> 3, rk = 2 * (tid & 7);
+        const gdouble* Xr[2];
+        const gdouble* Tr[2];
+        bool cval[2], rval[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = lr + 32 * j;
+            cval[j] = (col0 + q) < t.P;
+            rval[j] = (row0 + q) < t.M;
+            Xr[j] = X + colOff[q] + t.k0 + rk;
+            Tr[j] = T + (int64_t)(t.r0 + row0 + q) * nmu + t.k0 + rk;
+        }
         double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
         auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = kc + lk4 + i;
-                ra[i] = *pick(cval && k < t.K, Xrow + k);
-                rb[i] = *pick(rval && k < t.K, Trow + k);
-            }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const bool kv = kc + rk + e < t.K;
+                    ra[2 * j + e] = *pick(cval[j] && kv, Xr[j] + kc + e);
+                    rb[2 * j + e] = *pick(rval[j] && kv, Tr[j] + kc + e);
+                }
         };
         auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
             __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                As[(lk4 + i) * kLdsRow + lr] = ra[i];
-                Bs[(lk4 + i) * kLdsRow + lr] = rb[i];
-            }
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    As[(lr + 32 * j) * kRkRow + rk + e] = ra[2 * j + e];
+                    Bs[(lr + 32 * j) * kRkRow + rk + e] = rb[2 * j + e];
+                }
             __syncthreads();
         };
         k_pipeline(
             nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
             [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
-            [&]() { mfma_chunk<LP>(As, Bs, wr, wc, li, lk, acc); });
+            [&]() { mfma_chunk_l<LP, true, true>(As, Bs, wr, wc, li, lk, acc); });
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -388,7 +442,7 @@ hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cu_lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess) {
             constexpr int gran = 512;  // LDS allocation unit
-            constexpr int stat = (int)sizeof(double) * (2 * kKC * kLdsRow + 4 * kTile);  // the kernel's own
+            constexpr int stat = (int)sizeof(double) * (kUpdSmemDoubles + 4 * kTile);  // the kernel's own
             const int leaf = (leaf_lds + gran - 1) / gran * gran;
             const int u = (cu_lds / 3 / gran + 1) * gran;  // the least of which three do not fit
             if (2 * u + leaf <= cu_lds && u > stat && u <= 64 * 1024) pad = (size_t)(u - stat);
