@@ -1207,9 +1207,10 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
         return b;
     };
     int bad = 0;
+    std::vector<uint8_t> task_seen(s.tasks.size(), 0);
     for (size_t k = 0; k < s.waves.size(); ++k) {
         const Wave& wv = s.waves[k];
-        int64_t last_task = -1;
+        std::vector<int32_t> seen_tasks;  // tasks of this wave already replayed (tiles interleave)
         struct Delivery {
             int64_t at;
             int slo, shi;
@@ -1217,8 +1218,10 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
         std::vector<Delivery> deliveries;
         for (int64_t q = 0; q < wv.item_count; ++q) {
             const WorkItem& w = s.items[(size_t)(wv.item_first + q)];
-            if (w.task == last_task) continue;
-            last_task = w.task;
+            if (w.task < 0) continue;  // padding
+            if (task_seen[(size_t)w.task]) continue;
+            task_seen[(size_t)w.task] = 1;
+            seen_tasks.push_back(w.task);
             const UpdDesc& t = s.tasks[(size_t)w.task];
             const int mu = t.mode;
             int I[kMaxD];
@@ -1244,6 +1247,7 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
                 deliveries.push_back({lin(I) * D + mu, slo, shi});
             }
         }
+        for (int32_t t : seen_tasks) task_seen[(size_t)t] = 0;
         if (bad) break;
         for (int64_t q = 0; q < wv.leaf_count; ++q) {
             const LeafDesc& lf = s.leaves[(size_t)(wv.leaf_first + q)];
@@ -1287,6 +1291,36 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
     }
     for (int64_t k = 0; k < total; ++k)
         if (!solved[(size_t)k]) bad = 1;
+    // every task's output tiles appear exactly once (the items of a wave are
+    // interleaved over the XCDs and padded with task -1)
+    {
+        std::vector<std::vector<uint8_t>> hit(s.tasks.size());
+        std::vector<int> tiles_b(s.tasks.size(), 1);
+        for (size_t ti = 0; ti < s.tasks.size(); ++ti) {
+            const UpdDesc& t = s.tasks[ti];
+            const bool right = (t.mode == D - 1);
+            int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
+            int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
+            if (t.M <= 16) {
+                na = (t.P + 4 * kTile - 1) / (4 * kTile);
+                nb = 1;
+            }
+            hit[ti].assign((size_t)na * nb, 0);
+            tiles_b[ti] = nb;
+        }
+        for (const WorkItem& w : s.items) {
+            if (w.task < 0) continue;
+            if ((size_t)w.task >= s.tasks.size()) { bad = 1; break; }
+            auto& h = hit[(size_t)w.task];
+            const int nb = tiles_b[(size_t)w.task];
+            const size_t at = (size_t)w.ta * nb + w.tb;
+            if (w.ta < 0 || w.tb < 0 || w.tb >= nb || at >= h.size() || h[at]) { bad = 1; break; }
+            h[at] = 1;
+        }
+        for (const auto& h : hit)
+            for (uint8_t v : h)
+                if (!v) bad = 1;
+    }
     out[12] = bad;
     return TT_OK;
 }

@@ -259,6 +259,7 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
     double* Bs = smem + kKC * kLdsRow;
     const int tid = threadIdx.x;
     const WorkItem wi = items[first + blockIdx.x];
+    if (wi.task < 0) return;  // padding of the per-XCD tile layout (uniform)
     const UpdDesc t = tasks[wi.task];
     const ProbDesc& P = probs[t.prob];
     const int mode = t.mode;

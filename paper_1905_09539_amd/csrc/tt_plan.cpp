@@ -349,6 +349,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
 
     // Leaf flags: accumulator reads and the adjacent block.
     std::vector<int32_t> order;
+    std::vector<std::vector<WorkItem>> xq(8);  // per-XCD tile queues of one wave
     for (int64_t w = 0; w < W; ++w) {
         Wave wv;
         wv.leaf_first = (int64_t)s.leaves.size();
@@ -404,6 +405,13 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
                 return s.tasks[(size_t)a].K > s.tasks[(size_t)b].K;
             });
+            // Workgroups go to the XCDs round-robin (workgroup i to XCD i % 8):
+            // the tiles of one task that read the same source panel (same
+            // pencil columns) are dealt to one XCD, so the panel is fetched
+            // into one L2 instead of several.  Groups fill the least loaded
+            // XCD queue in order; the queues are interleaved, and the ragged
+            // tail is padded with empty items (task -1).
+            for (auto& q : xq) q.clear();
             for (int32_t tid : order) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
                 const bool right = (t.mode == D - 1);
@@ -413,14 +421,32 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                     na = (t.P + 4 * kTile - 1) / (4 * kTile);
                     nb = 1;
                 }
-                for (int a = 0; a < na; ++a)
-                    for (int b = 0; b < nb; ++b) s.items.push_back(WorkItem{tid, (int16_t)a, (int16_t)b});
+                // a group: the tiles sharing pencil columns (b for the left
+                // path, a for the right path; every wide tile alone)
+                const int ng = (t.M <= 16) ? na : (right ? na : nb);
+                const int gs = (t.M <= 16) ? 1 : (right ? nb : na);
+                for (int g = 0; g < ng; ++g) {
+                    size_t x = 0;
+                    for (size_t y = 1; y < xq.size(); ++y)
+                        if (xq[y].size() < xq[x].size()) x = y;
+                    for (int e = 0; e < gs; ++e) {
+                        int a = 0, b = 0;
+                        if (t.M <= 16) a = g;
+                        else if (right) { a = g; b = e; }
+                        else { a = e; b = g; }
+                        xq[x].push_back(WorkItem{tid, (int16_t)a, (int16_t)b});
+                    }
+                }
                 const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
                 wv.upd_flops += f;
                 fl_upd += f;
                 wv.upd_bytes += 8.0 * (((t.flags & 1) ? 1.0 : 2.0) * (double)t.M * t.P + (double)t.K * t.P +
                                        (double)t.M * t.K);
             }
+            size_t rounds = 0;
+            for (const auto& q : xq) rounds = std::max(rounds, q.size());
+            for (size_t r = 0; r < rounds; ++r)
+                for (const auto& q : xq) s.items.push_back(r < q.size() ? q[r] : WorkItem{-1, 0, 0});
         }
         wv.item_count = (int64_t)s.items.size() - wv.item_first;
         s.waves.push_back(wv);
