@@ -531,11 +531,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
         const gdouble* T = to_global(P.T[mu]);
         const int64_t n = P.n[mu];
         const int r1 = r0[mu] + sz[mu];
+        const int tpn = nxm | 1;  // odd row pitch of T_mu[B, B+1] in LDS
         for (int e = tid; e < sz[mu] * nxm; e += NT) {
             const int i = e / nxm, j = e - (e / nxm) * nxm;
-            Ta[e] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
+            Ta[i * tpn + j] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
         }
         __syncthreads();
+        // each lane starts its row loop at its own row: the fibres of
+        // consecutive lanes lie a power of two apart for some modes, and in
+        // step they would all update one LDS bank (with the odd pitch the T
+        // reads of different rows fall in different banks too)
+        const int rot = tid % sz[mu];
         // one thread per fibre along mu
         const int F = cap / sz[mu];
         const int64_t nstep = (int64_t)sz[mu] * gs[mu];  // from row r0+i to row r1+i
@@ -565,8 +571,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                     const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
                     xn[j] = v ? x : 0.0;
                 }
-                for (int i = 0; i < sz[mu]; ++i) {
-                    const double* ti = Ta + i * nxm + jc;
+                for (int ii = 0; ii < sz[mu]; ++ii) {
+                    const int i = (ii + rot < sz[mu]) ? ii + rot : ii + rot - sz[mu];
+                    const double* ti = Ta + i * tpn + jc;
                     double a0 = 0.0, a1 = 0.0;
 #pragma unroll
                     for (int j = 0; j < 8; j += 2) {
@@ -805,7 +812,7 @@ LeafGeom leaf_geometry(int D, const int* bmax, int maxtup, int maxcpl, int maxH)
     for (int mu = 0; mu < D; ++mu) {
         g.cap *= bmax[mu];
         g.tsum += bmax[mu] * (bmax[mu] + 4);
-        g.tamax = std::max(g.tamax, bmax[mu] * bmax[mu]);
+        g.tamax = std::max(g.tamax, bmax[mu] * (bmax[mu] | 1));  // T_mu[B, B+1] at an odd pitch
     }
     // union of the adjacent block (doubles) and the element records plus the
     // coupled-tuple list (u16 each)
