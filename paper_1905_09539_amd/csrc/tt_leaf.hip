@@ -536,7 +536,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
             const int i = e / nxm, j = e - (e / nxm) * nxm;
             Ta[i * tpn + j] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
         }
-        __syncthreads();
         // each lane starts its row loop at its own row: the fibres of
         // consecutive lanes lie a power of two apart for some modes, and in
         // step they would all update one LDS bank (with the odd pitch the T
@@ -545,44 +544,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
         // one thread per fibre along mu
         const int F = cap / sz[mu];
         const int64_t nstep = (int64_t)sz[mu] * gs[mu];  // from row r0+i to row r1+i
-        for (int f = tid; f < F; f += NT) {
-            int eb = 0;
-            int64_t gb = gbase;
-            {
-                int rem = f;
+        auto fibre_origin = [&](int f, int& eb, int64_t& gb) {
+            eb = 0;
+            gb = gbase;
+            int rem = f;
 #pragma unroll
-                for (int nu = D - 1; nu >= 0; --nu) {
-                    if (nu == mu) continue;
-                    const int q = qdiv(rem, rsz[nu]);
-                    const int c = rem - q * sz[nu];
-                    rem = q;
-                    eb += c * ls[nu];
-                    gb += (int64_t)c * gs[nu];
-                }
+            for (int nu = D - 1; nu >= 0; --nu) {
+                if (nu == mu) continue;
+                const int q = qdiv(rem, rsz[nu]);
+                const int c = rem - q * sz[nu];
+                rem = q;
+                eb += c * ls[nu];
+                gb += (int64_t)c * gs[nu];
             }
-            // the fibre of the next block, eight rows at a time in registers
-            // (clamped loads, zeroed past nxm); one row of T_mu[B, B+1] per
-            // output element
-            for (int jc = 0; jc < nxm; jc += 8) {
-                double xn[8];
+        };
+        // the fibre of the next block, sixteen rows at a time in registers
+        // (clamped loads, zeroed past nxm)
+        auto load16 = [&](int64_t gb, int jc, double (&xn)[16]) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool v = jc + j < nxm;
-                    const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
-                    xn[j] = v ? x : 0.0;
+            for (int j = 0; j < 16; ++j) {
+                const bool v = jc + j < nxm;
+                const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
+                xn[j] = v ? x : 0.0;
+            }
+        };
+        // one row of T_mu[B, B+1] per output element
+        auto apply16 = [&](int eb, int jc, const double (&xn)[16]) {
+            for (int ii = 0; ii < sz[mu]; ++ii) {
+                const int i = (ii + rot < sz[mu]) ? ii + rot : ii + rot - sz[mu];
+                const double* ti = Ta + i * tpn + jc;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; j += 2) {
+                    const double t0 = (jc + j < nxm) ? ti[(jc + j < nxm) ? j : 0] : 0.0;
+                    const double t1 = (jc + j + 1 < nxm) ? ti[(jc + j + 1 < nxm) ? j + 1 : 0] : 0.0;
+                    a0 = fma(t0, xn[j], a0);
+                    a1 = fma(t1, xn[j + 1], a1);
                 }
-                for (int ii = 0; ii < sz[mu]; ++ii) {
-                    const int i = (ii + rot < sz[mu]) ? ii + rot : ii + rot - sz[mu];
-                    const double* ti = Ta + i * tpn + jc;
-                    double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-                    for (int j = 0; j < 8; j += 2) {
-                        const double t0 = (jc + j < nxm) ? ti[(jc + j < nxm) ? j : 0] : 0.0;
-                        const double t1 = (jc + j + 1 < nxm) ? ti[(jc + j + 1 < nxm) ? j + 1 : 0] : 0.0;
-                        a0 = fma(t0, xn[j], a0);
-                        a1 = fma(t1, xn[j + 1], a1);
-                    }
-                    Xs[eb + i * ls[mu]] -= a0 + a1;
+                Xs[eb + i * ls[mu]] -= a0 + a1;
+            }
+        };
+        // the common case, at most one fibre per thread and one chunk: its
+        // loads are issued before the barrier that publishes the T block
+        const bool one = F <= NT && nxm <= 16;  // uniform
+        double xp[16];
+        int ebp = 0;
+        if (one && tid < F) {
+            int64_t gb = 0;
+            fibre_origin(tid, ebp, gb);
+            load16(gb, 0, xp);
+        }
+        __syncthreads();
+        if (one) {
+            if (tid < F) apply16(ebp, 0, xp);
+        } else {
+            for (int f = tid; f < F; f += NT) {
+                int eb = 0;
+                int64_t gb = 0;
+                fibre_origin(f, eb, gb);
+                for (int jc = 0; jc < nxm; jc += 16) {
+                    double xn[16];
+                    load16(gb, jc, xn);
+                    apply16(eb, jc, xn);
                 }
             }
         }
