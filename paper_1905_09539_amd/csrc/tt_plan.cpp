@@ -74,6 +74,23 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
     // one more block when a moved boundary leaves a block over b rows
     const int64_t m = (n + b - 1) / b;
     if (split(m) > b && m + 1 <= n) split(m + 1);
+    // Full blocks: b rows each (b - 1 where the boundary would cut a 2x2
+    // block), the remainder in a last, thinner block.  Taken when it needs no
+    // more blocks than the near-equal split: the update tiles of full blocks
+    // are full (a pencil of two b = 16 blocks is exactly 256 columns, K and M
+    // are multiples of 16), while near-equal blocks of 15 or 16 rows leave
+    // most tiles ragged.  A thin last block also folds into the split tree
+    // when the count is 2^L + 1.
+    if (b >= 2) {
+        std::vector<int32_t> full{0};
+        while (full.back() < n) {
+            int64_t q = (int64_t)full.back() + b;
+            if (q >= n) q = n;
+            else if (cuts_bump(q)) q -= 1;  // no two consecutive bumps: q - 1 is free
+            full.push_back((int32_t)q);
+        }
+        if (full.size() <= bst.size()) bst.swap(full);
+    }
     for (size_t i = 0; i + 1 < bst.size(); ++i)
         if (bst[i + 1] - bst[i] > kMaxLeaf) {
             err = "leaf block larger than " + std::to_string(kMaxLeaf) + " rows; use a smaller nmin";
