@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every step's kernels directly instead of replaying a recorded HIP graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -256,23 +258,29 @@ def main():
     plan = tt.Plan(T, B.shape, nmin=args.nmin)
     plan_s = time.perf_counter() - t0
     flops = plan.flops
-    stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        plan.solve(B, X)
-    plan.status()
-    torch.cuda.synchronize()
+    def timed(graph):
+        # a step: the whole solve (copy of B into X, every leaf wave and
+        # every update); with graph, replayed from the HIP graph recorded by
+        # the first warmup step on a created stream
+        stream = torch.cuda.Stream() if graph else torch.cuda.current_stream()
+        for _ in range(args.warmup):
+            plan.solve(B, X, stream=stream, graph=graph)
+        plan.status()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.solve(B, X, stream=stream, graph=graph)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        plan.status()
+        return e0.elapsed_time(e1) / args.steps
 
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.solve(B, X)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    plan.status()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms_eager = timed(False)
+    ms = ms_eager if args.no_graph else timed(True)
     tflops = flops / (ms * 1e-3) / 1e12
 
     # Per-kernel timing: the same steps again with HIP events around every
@@ -337,7 +345,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"d=3 triangular Laplace-like solve, n1=n2=n3={n}, T_mu real Schur form "
                                "(diag U[1,2], N(0,1)/sqrt(n) upper, 2x2 bump every 8th row), B~N(0,1)",
-                   "n": n, "flops": flops, "leaf_nmin": args.nmin or 16},
+                   "n": n, "flops": flops, "leaf_nmin": args.nmin or 16,
+                   "launch": "direct" if args.no_graph else "hip_graph_replay"},
+        "ms_per_step_direct_launch": ms_eager,
         "frac_of_fp64_peak": tflops / PEAK_FP64,
         "roofline": roof(dom),
         "roofline_other": roof(other),

@@ -214,6 +214,19 @@ int tt_plan_create_batched(tt_plan* out, int count, const int* d,
                            const int64_t* const* n, const double* const* const* T,
                            int trans, const tt_opts* opts);
 int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream);
+/* The same solve replayed from a HIP graph: the first call for a (B, X,
+ * stream) triple records the launch sequence of tt_plan_solve (status reset,
+ * input copy, every wave's leaf and update launches on the stream and the
+ * plan's side stream, joined by events) and instantiates it; later calls
+ * with the same triple launch the graph, saving the per-launch host and
+ * queue overhead of ~200 launches.  A different triple re-records (the
+ * previous graph is released after its stream drains).  Only for
+ * single-problem FP64 plans (mixed precision synchronises with the host);
+ * stream must be a created stream, not the default one.  B and X keep the
+ * meaning, layout and ownership of tt_plan_solve; the plan keeps the graph
+ * until it is destroyed.  Errors: TT_EINVAL (NULL plan or stream, batched or
+ * mixed-precision plan), TT_EHIP (capture or instantiation failed). */
+int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream);
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X,
                           void* stream);
 int tt_plan_status(tt_plan plan);

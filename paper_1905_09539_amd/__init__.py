@@ -44,7 +44,7 @@ SYMBOLS = [
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
-    "tt_plan_create_general_pair", "tt_plan_coefficient_grads",
+    "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
 ]
 
 
@@ -70,6 +70,7 @@ def lib():
         L.tt_plan_create_batched.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ip, vp, vp, ctypes.c_int,
                                              ctypes.POINTER(Opts)]
         L.tt_plan_solve.argtypes = [vp, vp, vp, vp]
+        L.tt_plan_solve_graph.argtypes = [vp, vp, vp, vp]
         L.tt_plan_solve_batched.argtypes = [vp, vp, vp, vp]
         L.tt_plan_status.argtypes = [vp]
         L.tt_plan_flops.argtypes = [vp]
@@ -275,14 +276,17 @@ class Plan:
     def flops(self):
         return lib().tt_plan_flops(self._h)
 
-    def solve(self, B, X=None, stream=None):
-        """Enqueue the solve (no host synchronisation)."""
+    def solve(self, B, X=None, stream=None, graph=False):
+        """Enqueue the solve (no host synchronisation).  graph=True replays
+        the launch sequence from a HIP graph recorded on the first call for
+        the same (B, X, stream) (single-problem FP64 plans, on a created,
+        non-default stream)."""
         import torch
         if self.count == 1:
             if X is None:
                 X = torch.empty_like(B)
-            _check(lib().tt_plan_solve(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)),
-                                       _stream(stream)))
+            fn = lib().tt_plan_solve_graph if graph else lib().tt_plan_solve
+            _check(fn(self._h, ctypes.c_void_p(_dev(B)), ctypes.c_void_p(_dev(X)), _stream(stream)))
             return X
         if X is None:
             X = [torch.empty_like(b) for b in B]

@@ -113,8 +113,16 @@ struct tt_plan_s {
     double* part = nullptr;      // norm partial sums (device)
     double* part_host = nullptr; // pinned host copy
     double last_info[2] = {0, 0};
+    // the solve recorded as a HIP graph (tt_plan_solve_graph) and the
+    // (B, X, stream) it was recorded for
+    hipGraphExec_t gexec = nullptr;
+    const double* gB = nullptr;
+    double* gX = nullptr;
+    hipStream_t gst = nullptr;
 
     ~tt_plan_s() {
+        if (gst) (void)hipStreamSynchronize(gst);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         if (side) (void)hipStreamSynchronize(side);
         for (hipEvent_t e : evL) (void)hipEventDestroy(e);
         for (hipEvent_t e : evU) (void)hipEventDestroy(e);
@@ -832,6 +840,43 @@ int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream) {
     if (!plan) return fail(TT_EINVAL, "plan is NULL");
     if (plan->count != 1) return fail(TT_EINVAL, "batched plan: use tt_plan_solve_batched");
     return solve_single(plan, B, X, (hipStream_t)stream);
+}
+
+int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream) {
+    if (!plan) return fail(TT_EINVAL, "plan is NULL");
+    if (plan->count != 1 || plan->prec != TT_FP64)
+        return fail(TT_EINVAL, "graph solve needs a single-problem FP64 plan");
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) return fail(TT_EINVAL, "graph solve needs a created stream (the default stream cannot be captured)");
+    if (!(plan->gexec && plan->gB == B && plan->gX == X && plan->gst == st)) {
+        if (plan->gexec) {
+            if (plan->gst) TT_HIP_CHECK(hipStreamSynchronize(plan->gst));
+            (void)hipGraphExecDestroy(plan->gexec);
+            plan->gexec = nullptr;
+        }
+        // the launch sequence of one solve (status reset, input copy, every
+        // wave's leaf and update launches, the side stream forked and joined
+        // by events): kernels and event edges only
+        hipGraph_t g = nullptr;
+        TT_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int rc = solve_single(plan, B, X, st);
+        const hipError_t ce = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        TT_HIP_CHECK(ce);
+        const hipError_t ie = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) plan->gexec = nullptr;
+        TT_HIP_CHECK(ie);
+        plan->gB = B;
+        plan->gX = X;
+        plan->gst = st;
+    }
+    plan->last_stream = st;
+    TT_HIP_CHECK(hipGraphLaunch(plan->gexec, st));
+    return TT_OK;
 }
 
 int tt_plan_info(tt_plan plan, double* out) {

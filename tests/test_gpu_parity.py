@@ -148,3 +148,35 @@ def test_in_place_and_plan_reuse():
         plan.status()
         assert rel(Bd.cpu().numpy(), Xo) <= TOL
     assert plan.flops == oracle.flops_tri(p["T"], p["B"].shape)
+
+
+def test_graph_solve_replays_match_eager_and_oracle():
+    """tt_plan_solve_graph: the recorded launch sequence replayed several
+    times on a created stream, with eager work and synchronisations between
+    the replays; every replay is bit-identical to the eager solve (the same
+    kernels in the same order, no atomics) and within TOL of the oracle."""
+    p = ti.laplace_tri((60, 50, 40), seed=11, bumps="random")
+    T = [dev(t) for t in p["T"]]
+    B = dev(p["B"])
+    plan = tt().Plan(T, p["B"].shape)
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    s = torch.cuda.Stream()
+    Xe = torch.empty_like(B)
+    Xg = torch.empty_like(B)
+    with torch.cuda.stream(s):
+        plan.solve(B, Xe, stream=s)
+        plan.status()
+        for rep in range(3):
+            Xg.fill_(float("nan"))
+            plan.solve(B, Xg, stream=s, graph=True)
+            plan.status()
+            assert torch.equal(Xg, Xe), rep
+            _ = float((B * 2.0).sum().item())  # eager work between replays
+        # another output buffer records a second graph
+        X2 = torch.empty_like(B)
+        plan.solve(B, X2, stream=s, graph=True)
+        plan.status()
+        assert torch.equal(X2, Xe)
+    assert rel(Xg.cpu().numpy(), Xo) <= TOL
+    with pytest.raises(tt().TTError):  # the default stream cannot be captured
+        plan.solve(B, Xg, stream=torch.cuda.default_stream(), graph=True)
