@@ -119,9 +119,14 @@ struct tt_plan_s {
     const double* gB = nullptr;
     double* gX = nullptr;
     hipStream_t gst = nullptr;
+    hipEvent_t gdone = nullptr;  // recorded after every graph launch (the caller's
+                                 // stream may be gone when the plan is destroyed)
 
     ~tt_plan_s() {
-        if (gst) (void)hipStreamSynchronize(gst);
+        if (gdone) {
+            (void)hipEventSynchronize(gdone);
+            (void)hipEventDestroy(gdone);
+        }
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (side) (void)hipStreamSynchronize(side);
         for (hipEvent_t e : evL) (void)hipEventDestroy(e);
@@ -850,10 +855,11 @@ int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream) 
     if (!st) return fail(TT_EINVAL, "graph solve needs a created stream (the default stream cannot be captured)");
     if (!(plan->gexec && plan->gB == B && plan->gX == X && plan->gst == st)) {
         if (plan->gexec) {
-            if (plan->gst) TT_HIP_CHECK(hipStreamSynchronize(plan->gst));
+            TT_HIP_CHECK(hipEventSynchronize(plan->gdone));  // its last launch has finished
             (void)hipGraphExecDestroy(plan->gexec);
             plan->gexec = nullptr;
         }
+        if (!plan->gdone) TT_HIP_CHECK(hipEventCreateWithFlags(&plan->gdone, hipEventDisableTiming));
         // the launch sequence of one solve (status reset, input copy, every
         // wave's leaf and update launches, the side stream forked and joined
         // by events): kernels and event edges only
@@ -876,6 +882,7 @@ int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream) 
     }
     plan->last_stream = st;
     TT_HIP_CHECK(hipGraphLaunch(plan->gexec, st));
+    TT_HIP_CHECK(hipEventRecord(plan->gdone, st));
     return TT_OK;
 }
 
