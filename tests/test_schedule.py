@@ -81,3 +81,13 @@ def test_schedule_rejects_bad_structure():
     assert e.value.code == tt.TT_EINVAL
     with pytest.raises(tt.TTError):
         tt.schedule_info([np.eye(4)] * 3, (4, 4, 4), nmin=64)
+
+
+def test_plan_entry_points_reject_null_plan():
+    """The plan entry points validate their arguments before any device
+    call: a NULL plan is TT_EINVAL with a message (no GPU needed)."""
+    L = tt.lib()
+    null = ctypes.c_void_p(0)
+    for fn in (L.tt_plan_solve, L.tt_plan_solve_graph):
+        assert fn(null, null, null, null) == tt.TT_EINVAL
+        assert b"NULL" in L.tt_last_error()
