@@ -251,8 +251,10 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
                                                           const WorkItem* __restrict__ items,
                                                           int64_t first,
                                                           const ProbDesc* __restrict__ probs, int D) {
-    // one LDS buffer, carved per path: 64x64 tiles use two 16 x 80 operand
-    // blocks, wide tiles a 16 x 17 T block and a 16 x 272 pencil block
+    // one LDS buffer, carved per path: 64x64 tiles a 64 x 17 T block ([r][k])
+    // at As and, at Bs, a 16 x 80 pencil block ([k][c]; fastest mode: a
+    // 64 x 17 [c][k] block); wide tiles a 16 x 17 T block and a 16 x 272
+    // pencil block (fastest mode: 256 x 17)
     __shared__ double smem[kUpdSmemDoubles];
     __shared__ int64_t colOff[4 * kTile];
     double* As = smem;
