@@ -247,7 +247,31 @@ int finish_plan(tt_plan_s* P, int nmin) {
     int rc = build_schedule(P->sched, nmin, err);
     if (rc) return fail(rc, err);
     Schedule& s = P->sched;
+    // One device buffer for every problem's coefficients and block starts
+    // (filled by one copy from a packed host image) and one for the update
+    // accumulators: a batched plan makes two allocations instead of several
+    // per problem and mode.
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t cbytes = 0, abytes = 0;
+    for (const HostProblem& hp : s.probs)
+        for (int mu = 0; mu < s.D; ++mu) {
+            cbytes += al(sizeof(double) * std::max<size_t>(1, hp.T[mu].size()));
+            cbytes += al(sizeof(int32_t) * hp.bst[mu].size());
+            // accumulator of the updates of mode mu (mode 0 updates X itself)
+            if (mu >= 1 && hp.N > 0) abytes += al(sizeof(double) * (size_t)hp.N);
+        }
+    char* dc = nullptr;
+    char* da = nullptr;
+    if (hipMalloc((void**)&dc, std::max<size_t>(cbytes, 256)) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
+    P->owned.push_back(dc);
+    if (abytes > 0) {
+        if (hipMalloc((void**)&da, abytes) != hipSuccess)
+            return fail(TT_ENOMEM, "hipMalloc failed (update accumulators)");
+        P->owned.push_back(da);
+    }
+    std::vector<char> image(cbytes, 0);
     std::vector<ProbDesc> pd(s.probs.size());
+    size_t co = 0, ao = 0;
     for (size_t i = 0; i < s.probs.size(); ++i) {
         HostProblem& hp = s.probs[i];
         ProbDesc& d = pd[i];
@@ -257,29 +281,19 @@ int finish_plan(tt_plan_s* P, int nmin) {
             d.stride[mu] = (mu < s.D) ? hp.stride[mu] : 0;
         }
         for (int mu = 0; mu < s.D; ++mu) {
-            double* t = nullptr;
-            int32_t* b = nullptr;
-            size_t tb = sizeof(double) * std::max<size_t>(1, hp.T[mu].size());
-            if (hipMalloc((void**)&t, tb) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-            P->owned.push_back(t);
-            if (!hp.T[mu].empty())
-                TT_HIP_CHECK(hipMemcpy(t, hp.T[mu].data(), sizeof(double) * hp.T[mu].size(), hipMemcpyHostToDevice));
-            if (hipMalloc((void**)&b, sizeof(int32_t) * hp.bst[mu].size()) != hipSuccess)
-                return fail(TT_ENOMEM, "hipMalloc failed");
-            P->owned.push_back(b);
-            TT_HIP_CHECK(hipMemcpy(b, hp.bst[mu].data(), sizeof(int32_t) * hp.bst[mu].size(), hipMemcpyHostToDevice));
-            d.T[mu] = t;
-            d.bst[mu] = b;
-            // accumulator of the updates of mode mu (mode 0 updates X itself)
+            if (!hp.T[mu].empty()) std::memcpy(image.data() + co, hp.T[mu].data(), sizeof(double) * hp.T[mu].size());
+            d.T[mu] = (double*)(dc + co);
+            co += al(sizeof(double) * std::max<size_t>(1, hp.T[mu].size()));
+            std::memcpy(image.data() + co, hp.bst[mu].data(), sizeof(int32_t) * hp.bst[mu].size());
+            d.bst[mu] = (int32_t*)(dc + co);
+            co += al(sizeof(int32_t) * hp.bst[mu].size());
             if (mu >= 1 && hp.N > 0) {
-                double* acc = nullptr;
-                if (hipMalloc((void**)&acc, sizeof(double) * (size_t)hp.N) != hipSuccess)
-                    return fail(TT_ENOMEM, "hipMalloc failed (update accumulators)");
-                P->owned.push_back(acc);
-                d.A[mu] = acc;
+                d.A[mu] = (double*)(da + ao);
+                ao += al(sizeof(double) * (size_t)hp.N);
             }
         }
     }
+    if (cbytes > 0) TT_HIP_CHECK(hipMemcpy(dc, image.data(), cbytes, hipMemcpyHostToDevice));
     if ((rc = upload(pd, &P->d_probs))) return rc;
     if ((rc = upload(s.leaves, &P->d_leaves))) return rc;
     if ((rc = upload(s.shapes, &P->d_shapes))) return rc;
