@@ -227,6 +227,12 @@ int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream);
  * until it is destroyed.  Errors: TT_EINVAL (NULL plan or stream, batched or
  * mixed-precision plan), TT_EHIP (capture or instantiation failed). */
 int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream);
+/* Plain device copy of n doubles, src -> dst (device pointers, not
+ * overlapping), enqueued on stream with the library's copy kernel: one read
+ * and one write of 8 n bytes, the reference against which hardware byte
+ * counters are calibrated.  Errors: TT_EINVAL (n < 0, NULL pointer with
+ * n > 0), TT_EHIP. */
+int tt_copy_device(const double* src, double* dst, int64_t n, void* stream);
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X,
                           void* stream);
 int tt_plan_status(tt_plan plan);

@@ -45,6 +45,7 @@ SYMBOLS = [
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
+    "tt_copy_device",
 ]
 
 
@@ -71,6 +72,7 @@ def lib():
                                              ctypes.POINTER(Opts)]
         L.tt_plan_solve.argtypes = [vp, vp, vp, vp]
         L.tt_plan_solve_graph.argtypes = [vp, vp, vp, vp]
+        L.tt_copy_device.argtypes = [vp, vp, ctypes.c_int64, vp]
         L.tt_plan_solve_batched.argtypes = [vp, vp, vp, vp]
         L.tt_plan_status.argtypes = [vp]
         L.tt_plan_flops.argtypes = [vp]
@@ -367,6 +369,15 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def copy_device(src, dst, stream=None):
+    """dst <- src (same-size contiguous float64 device tensors) with the
+    library's copy kernel (the benchmark's byte-counter reference)."""
+    if src.numel() != dst.numel():
+        raise ValueError("copy_device: sizes differ")
+    _check(lib().tt_copy_device(ctypes.c_void_p(_dev(src)), ctypes.c_void_p(_dev(dst)), src.numel(),
+                                _stream(stream)))
 
 
 def schedule_info(T_host, shape, nmin=0):

@@ -29,11 +29,15 @@ static int fail(int code, const std::string& msg) {
 
 struct PtrPack {
     double* p[64];
+    const double* b[64];
 };
 
 __global__ void set_x_ptrs_kernel(ProbDesc* probs, PtrPack pack, int first, int count) {
     int i = threadIdx.x;
-    if (i < count) probs[first + i].X = pack.p[i];
+    if (i < count) {
+        probs[first + i].X = pack.p[i];
+        probs[first + i].B = pack.b[i];
+    }
 }
 
 // In-place reversal of the element order of a tensor (all modes reversed).
@@ -312,11 +316,16 @@ int finish_plan(tt_plan_s* P, int nmin) {
     return TT_OK;
 }
 
-int set_pointers(tt_plan_s* P, double* const* X, int count, hipStream_t st) {
+// Solution and right-hand-side pointers of the problems (B = NULL: the
+// right-hand side is already in X).
+int set_pointers(tt_plan_s* P, double* const* X, int count, hipStream_t st, const double* const* B = nullptr) {
     for (int first = 0; first < count; first += 64) {
         PtrPack pack;
         int c = std::min(64, count - first);
-        for (int i = 0; i < c; ++i) pack.p[i] = X[first + i];
+        for (int i = 0; i < c; ++i) {
+            pack.p[i] = X[first + i];
+            pack.b[i] = B ? B[first + i] : X[first + i];
+        }
         hipLaunchKernelGGL(set_x_ptrs_kernel, dim3(1), dim3(64), 0, st, P->d_probs, pack, first, c);
         TT_HIP_CHECK(hipGetLastError());
     }
@@ -371,7 +380,7 @@ int prepare_inputs(tt_plan_s* P, const double* const* B, double* const* X, hipSt
         if (hp.N == 0) continue;
         if (!B[i] || !X[i]) return fail(TT_EINVAL, "tensor pointer is NULL");
         if (!P->trans) {
-            if (B[i] != X[i]) TT_HIP_CHECK(launch_copy(B[i], X[i], hp.N, st));
+            // no copy: the first mode-0 update of a block, or its leaf, reads B
         } else {
             if (B[i] != X[i]) {
                 hipLaunchKernelGGL(reverse_copy_kernel, dim3(grid_for(hp.N)), dim3(256), 0, st, B[i], X[i], hp.N);
@@ -381,7 +390,7 @@ int prepare_inputs(tt_plan_s* P, const double* const* B, double* const* X, hipSt
             TT_HIP_CHECK(hipGetLastError());
         }
     }
-    return set_pointers(P, X, P->count, st);
+    return set_pointers(P, X, P->count, st, P->trans ? nullptr : B);
 }
 
 int finish_outputs(tt_plan_s* P, double* const* X, hipStream_t st) {
@@ -861,6 +870,12 @@ int tt_plan_solve(tt_plan plan, const double* B, double* X, void* stream) {
     return solve_single(plan, B, X, (hipStream_t)stream);
 }
 
+int tt_copy_device(const double* src, double* dst, int64_t n, void* stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) return fail(TT_EINVAL, "bad copy arguments");
+    TT_HIP_CHECK(launch_copy(src, dst, n, (hipStream_t)stream));
+    return TT_OK;
+}
+
 int tt_plan_solve_graph(tt_plan plan, const double* B, double* X, void* stream) {
     if (!plan) return fail(TT_EINVAL, "plan is NULL");
     if (plan->count != 1 || plan->prec != TT_FP64)
@@ -1337,7 +1352,8 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
                     eq += b * b;
                 }
                 if (psum[at] != es || psq[at] != eq) bad = 1;
-                if (mu >= 1 && (((lf.flags >> mu) & 1) != (pending[(size_t)lin(I) * D + mu] > 0 ? 1 : 0))) bad = 1;
+                // bit 0: right-hand side in X (mode-0 updates arrived); bits mu >= 1: accumulators
+                if (((lf.flags >> mu) & 1) != (pending[(size_t)lin(I) * D + mu] > 0 ? 1 : 0)) bad = 1;
             }
         }
         for (int64_t q = 0; q < wv.leaf_count; ++q) {

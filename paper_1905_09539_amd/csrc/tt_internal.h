@@ -31,7 +31,10 @@ __device__ inline __attribute__((address_space(1))) T* to_global(T* p) {
 
 // Per-problem description as the kernels see it (device table).
 struct ProbDesc {
-    double* X;                   // solution / right-hand side, in place
+    double* X;                   // solution; mode-0 updates accumulate into it
+    const double* B;             // right-hand side (may equal X): read by the
+                                 // first mode-0 update of a block, or by its
+                                 // leaf when the block has none
     double* A[kMaxD];            // per-mode update accumulators (modes >= 1;
                                  // mode 0 updates go straight into X)
     const double* T[kMaxD];      // coefficients (device, row-major n x n)
@@ -44,7 +47,9 @@ struct ProbDesc {
 struct LeafDesc {
     int32_t prob;
     int16_t blk[kMaxD];
-    int32_t flags;               // bit mu: subtract accumulator A[mu];
+    int32_t flags;               // bit 0: the block's right-hand side is in X
+                                 // (it received mode-0 updates), else in B;
+                                 // bit mu >= 1: subtract accumulator A[mu];
                                  // bit 4+mu: the next block along mu exists
                                  // (its contribution is applied in the leaf)
     int32_t shape;               // index of the tuple-grid shape (LeafShape)
@@ -84,7 +89,8 @@ struct UpdDesc {
     int32_t ext[3];
     int16_t mode;                // mode mu of the update
     int16_t flags;               // bit 0: first contribution to these targets
-                                 // (store instead of accumulate)
+                                 // (store instead of accumulate; mode 0 adds
+                                 // the right-hand side B to what it stores)
     int64_t ostr[3];             // strides of the other modes
 };
 

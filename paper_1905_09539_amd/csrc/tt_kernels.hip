@@ -142,7 +142,8 @@ __device__ inline void k_pipeline(int nchunk, Load&& load, Stage&& stage, Comput
 template <bool LP>
 __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
                                 gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
-                                bool right, bool store, double sgn, double* As, double* Bs, int64_t* colOff) {
+                                bool right, bool store, const gdouble* B0, double sgn, double* As, double* Bs,
+                                int64_t* colOff) {
     constexpr int kW = 4 * kTile;   // 256 pencil columns
     constexpr int kWRow = kW + 16;  // LDS row pitch of the 256-wide operand
     constexpr int kTRow = 17;       // LDS pitch of the 16x16 T block (odd: conflict-free staging)
@@ -240,9 +241,9 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
             const int c = wave * 64 + b * 16 + (right ? i : li);
             const int r = right ? li : i;
             if (col0 + c >= t.P || r >= t.M) continue;
-            gdouble* p = C + colOff[c] + (int64_t)(t.r0 + r) * smu;
+            const int64_t o = colOff[c] + (int64_t)(t.r0 + r) * smu;
             const double val = sgn * (double)acc[b][v];
-            *p = store ? val : *p + val;
+            C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
         }
 }
 
@@ -273,8 +274,10 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
     const bool right = (mode == D - 1);
     const bool store = (t.flags & 1) != 0;
     const double sgn = (mode == 0) ? -1.0 : 1.0;
+    // the first mode-0 update of a block starts from the right-hand side B
+    const gdouble* B0 = (mode == 0 && store) ? to_global(P.B) : nullptr;
     if (t.M <= 16) {  // uniform over the workgroup
-        upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, sgn, smem, smem + kWideTDoubles, colOff);
+        upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, smem + kWideTDoubles, colOff);
         return;
     }
     const int col0 = (right ? wi.ta : wi.tb) * kTile;  // pencil columns
@@ -348,9 +351,9 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
                 for (int v = 0; v < 4; ++v) {
                     const int r = wr + 16 * i + mfma_row<LP>(v, lk);
                     if (row0 + r < t.M) {
-                        gdouble* p = C + coff + (int64_t)(t.r0 + row0 + r) * smu;
+                        const int64_t o = coff + (int64_t)(t.r0 + row0 + r) * smu;
                         const double val = sgn * (double)acc[i][j][v];
-                        *p = store ? val : *p + val;
+                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
                     }
                 }
         }
@@ -409,9 +412,9 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
                 for (int j = 0; j < 2; ++j) {
                     const int r = wc + 16 * j + li;
                     if (row0 + r < t.M) {
-                        gdouble* p = C + coff + t.r0 + row0 + r;
+                        const int64_t o = coff + t.r0 + row0 + r;
                         const double val = sgn * (double)acc[i][j][v];
-                        *p = store ? val : *p + val;
+                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
                     }
                 }
             }

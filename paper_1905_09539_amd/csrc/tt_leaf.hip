@@ -460,7 +460,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
         return g + (int64_t)e * gs[0];
     };
 
-    // ---- 1. right-hand side and diagonal blocks
+    // ---- 1. right-hand side and diagonal blocks: from X when mode-0 updates
+    // have reached the block (they start from B), else from B itself
+    const gdouble* __restrict__ rhs = (L.flags & 1) ? X : to_global(P.B);
     for (int base = 0; base < cap; base += NT * kLoadBatch) {
         double v[kLoadBatch];
         int64_t g[kLoadBatch];
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
         for (int u = 0; u < kLoadBatch; ++u) {
             const int e = base + u * NT + tid;
             g[u] = (e < cap) ? gbase + goff(e) : -1;
-            v[u] = (g[u] >= 0) ? X[g[u]] : 0.0;
+            v[u] = (g[u] >= 0) ? rhs[g[u]] : 0.0;
         }
 #pragma unroll
         for (int mu = 1; mu < D; ++mu) {

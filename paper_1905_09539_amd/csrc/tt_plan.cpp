@@ -291,7 +291,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             nrec += r;
             r = 1;
         }
-        if (mu > 0 && nrec == 0) t.flags |= 1;
+        if (nrec == 0) t.flags |= 1;  // first contribution (mode 0: from B into X)
         if (nrec != 0 && nrec != hi_t - lo) t.flags |= 2;  // inconsistent (checked below)
         triggered[(size_t)trigger_wave].push_back((int32_t)s.tasks.size());
         s.tasks.push_back(t);
@@ -378,7 +378,9 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             std::array<int, kMaxD> tm = {1, 1, 1, 1};
             int all = 1, single = 1;
             for (int mu = 0; mu < D; ++mu) {
-                if (mu > 0 && received[(size_t)L.prob][(size_t)(block_lin(p, I) * D + mu)]) L.flags |= 1 << mu;
+                // bit 0: the right-hand side is in X (mode-0 updates); bits
+                // mu >= 1: accumulators to subtract
+                if (received[(size_t)L.prob][(size_t)(block_lin(p, I) * D + mu)]) L.flags |= 1 << mu;
                 if (I[mu] + 1 < p.m[mu]) L.flags |= 1 << (4 + mu);
                 const BlockInfo& bi = binfo[(size_t)L.prob][(size_t)mu][(size_t)I[mu]];
                 tm[mu] = bi.tuples;
@@ -400,7 +402,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                 double off = (double)sz[mu] * (double)(sz[mu] - 1) / 2.0 + (double)bumps;
                 lf += 2.0 * off * (double)(ne / sz[mu]);
                 lb += 8.0 * (double)(sz[mu] * sz[mu]);
-                if (L.flags & (1 << mu)) lb += 8.0 * (double)ne;
+                if (mu >= 1 && (L.flags & (1 << mu))) lb += 8.0 * (double)ne;  // accumulator read
                 if (L.flags & (1 << (4 + mu))) {
                     int64_t sa = p.bst[mu][I[mu] + 2] - p.bst[mu][I[mu] + 1];
                     lf += 2.0 * (double)sz[mu] * (double)sa * (double)(ne / sz[mu]);
@@ -457,7 +459,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                 const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
                 wv.upd_flops += f;
                 fl_upd += f;
-                wv.upd_bytes += 8.0 * (((t.flags & 1) ? 1.0 : 2.0) * (double)t.M * t.P + (double)t.K * t.P +
+                wv.upd_bytes += 8.0 * (((t.flags & 1) && t.mode != 0 ? 1.0 : 2.0) * (double)t.M * t.P + (double)t.K * t.P +
                                        (double)t.M * t.K);
             }
             size_t rounds = 0;
