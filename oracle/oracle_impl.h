@@ -190,15 +190,25 @@ void FN(oracle_mode_product)(int d, const int64_t* n, int mu, const double* M, i
     for (int nu = 0; nu < mu; ++nu) outer *= n[nu];
     for (int nu = mu + 1; nu < d; ++nu) inner *= n[nu];
     int64_t nm = n[mu];
-    #pragma omp parallel for schedule(static)
-    for (int64_t o = 0; o < outer; ++o)
+    /* Y[o, r, q] = sum_j M[r, j] X[o, j, q], the sum taken in increasing j.
+     * The q range is cut into chunks of QC columns only so that the
+     * X[o, :, chunk] panel a task reads stays in cache (and so that the
+     * slowest mode, with outer = 1, still has parallel tasks); every output
+     * is the same sum in the same order. */
+    const int64_t QC = 64;
+    const int64_t nq = (inner + QC - 1) / QC;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t task = 0; task < outer * nq; ++task) {
+        const int64_t o = task / nq, q0 = (task % nq) * QC;
+        const int64_t q1 = (q0 + QC < inner) ? q0 + QC : inner;
         for (int64_t r = 0; r < m; ++r)
-            for (int64_t q = 0; q < inner; ++q) {
+            for (int64_t q = q0; q < q1; ++q) {
                 REAL acc = 0;
                 for (int64_t j = 0; j < nm; ++j)
                     acc += (REAL)M[r * nm + j] * (REAL)X[(o * nm + j) * inner + q];
                 Y[(o * m + r) * inner + q] = (double)acc;
             }
+    }
 }
 
 /* Pair operator (the two-matrices-per-mode family of the conclusions):

@@ -76,41 +76,6 @@ def test_closed_form_diagonal_full_size():
     assert rel(X, Xc) < 1e-15
 
 
-def _corner(p, lo):
-    """The solution on the far corner box [lo_mu, n_mu) depends only on that
-    box: it solves the same equation with the trailing blocks of T."""
-    T = [t[l:, l:] for t, l in zip(p["T"], lo)]
-    B = p["B"][tuple(slice(l, None) for l in lo)]
-    return T, np.ascontiguousarray(B)
-
-
-def test_full_size_512_sampled():
-    """n = 512 with the cfg1 triangular factors: exact corner-box parity with
-    the oracle, plus the residual at sampled elements anywhere in the tensor."""
-    n = 512
-    p = ti.laplace_tri((n, n, n), seed=1, bumps="every8")
-    print("case 512^3 solve", flush=True)
-    X = gpu_solve(p["T"], p["B"])
-    lo = (385, 385, 385)  # bumps start at 7 mod 8, so T[385, 384] == 0
-    for t, l in zip(p["T"], lo):
-        assert t[l, l - 1] == 0.0
-    Tc, Bc = _corner(p, lo)
-    Xo = oracle.lap_solve(Tc, Bc)
-    assert rel(X[tuple(slice(l, None) for l in lo)], Xo) <= TOL
-    # sampled residual r_i = B_i - sum_mu sum_j T_mu[i_mu, j] X[.., j, ..]
-    g = np.random.default_rng(7)
-    idx = g.integers(0, n, size=(2000, 3))
-    T1, T2, T3 = p["T"]
-    res = np.empty(len(idx))
-    scale = np.empty(len(idx))
-    for k, (i, j, l) in enumerate(idx):
-        v = T1[i] @ X[:, j, l] + T2[j] @ X[i, :, l] + T3[l] @ X[i, j, :]
-        res[k] = p["B"][i, j, l] - v
-        scale[k] = (np.abs(T1[i]) @ np.abs(X[:, j, l]) + np.abs(T2[j]) @ np.abs(X[i, :, l])
-                    + np.abs(T3[l]) @ np.abs(X[i, j, :]) + abs(p["B"][i, j, l]))
-    assert np.max(np.abs(res) / scale) < 64 * np.finfo(float).eps
-
-
 def test_singular_reported():
     T1 = np.diag([1.0, 2.0, 3.0])
     T2 = np.diag([0.5, -2.0, 4.0])
