@@ -63,13 +63,36 @@ typedef struct {
     int prec;           /* tt_prec                                           */
     double tol;         /* refinement stop: ||D||_F / ||X||_F <= tol         */
     int max_iter;       /* refinement iteration cap                          */
+    int deterministic;  /* accepted for interface stability: every path is
+                           bitwise reproducible run to run (each output is
+                           written by one workgroup per launch, accumulation
+                           orders are fixed, no floating-point atomics)      */
     void* stream;       /* hipStream_t                                       */
+    void* workspace;    /* DEVICE memory owned by the caller, or NULL.  When
+                           set, every device buffer of the call (or of the
+                           plan built from these options) is carved from it
+                           and the library calls no device allocator; it must
+                           stay valid, and not be used by anything else,
+                           until the call returns (for a plan: until
+                           tt_plan_destroy).  tt_workspace_bytes gives a
+                           sufficient size; a smaller one fails with
+                           TT_ENOMEM and the needed size in tt_last_error. */
+    size_t workspace_bytes;
     double info[4];     /* out: [0] refinement iterations, [1] last
                            ||D||_F/||X||_F, [2] plan build seconds,
                            [3] device solve milliseconds (when timed)        */
 } tt_opts;
 
-/* Fill *o with defaults (nmin 0, TT_FP64, tol 1e-13, max_iter 10, stream NULL). */
+/* Upper bound of the device workspace (bytes) that one single-problem call
+ * of solve_tri_tensor (Laplace-like or pair form), solve_general_tensor or
+ * solve_backward with order d, mode sizes n[0..d-1], precision prec
+ * (tt_prec) and the default leaf size (opts->nmin = 0) needs, whatever the
+ * coefficients' 2x2-block pattern.  Host-only; 0 on invalid arguments.
+ * Batched calls need the sum over their problems. */
+size_t tt_workspace_bytes(int d, const int64_t* n, int prec);
+
+/* Fill *o with defaults (nmin 0, TT_FP64, tol 1e-13, max_iter 10, stream and
+ * workspace NULL). */
 int tt_opts_default(tt_opts* o);
 
 /* Human-readable name of a status code (static storage). */
@@ -262,10 +285,13 @@ int tt_plan_destroy(tt_plan plan);
 
 /* Host-only schedule query (no GPU): plans the triangular solve of one
  * problem with HOST coefficients T_host[mu] (row-major) and leaf edge nmin,
- * and fills out[13]: flops, leaf flops, update flops, waves, leaves, update
+ * and fills out[14]: flops, leaf flops, update flops, waves, leaves, update
  * tasks, update tiles, kernel launches, the largest leaf edge per internal
- * mode (4 entries), and a dependency check of the schedule (0 = every update
- * reads only solved blocks and every leaf has all its contributions).
+ * mode (4 entries), a dependency check of the schedule (0 = every update
+ * reads only solved blocks and every leaf has all its contributions), and
+ * the device bytes a plan of this schedule takes (tables, coefficient
+ * copies and update accumulators; the part of tt_workspace_bytes that
+ * depends on the coefficients' 2x2-block pattern).
  * Errors: as tt_plan_create. */
 int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int nmin, double* out);
 

@@ -31,7 +31,8 @@ _STATUS = {0: "TT_OK", 1: "TT_EINVAL", 2: "TT_ESINGULAR", 3: "TT_ENOMEM", 4: "TT
 
 class Opts(ctypes.Structure):
     _fields_ = [("nmin", ctypes.c_int), ("prec", ctypes.c_int), ("tol", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("max_iter", ctypes.c_int), ("deterministic", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("info", ctypes.c_double * 4)]
 
 
@@ -45,7 +46,7 @@ SYMBOLS = [
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
-    "tt_copy_device",
+    "tt_copy_device", "tt_workspace_bytes",
 ]
 
 
@@ -60,6 +61,8 @@ def lib():
         L.tt_last_error.restype = ctypes.c_char_p
         L.tt_status_str.restype = ctypes.c_char_p
         L.tt_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        L.tt_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int]
+        L.tt_workspace_bytes.restype = ctypes.c_size_t
         L.solve_tri_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_general_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_backward.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts)]
@@ -119,27 +122,44 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _opts(nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None):
+def _opts(nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, workspace=None):
     o = Opts()
     lib().tt_opts_default(ctypes.byref(o))
     o.nmin, o.prec, o.tol, o.max_iter = int(nmin), int(prec), float(tol), int(max_iter)
     o.stream = _stream(stream).value
+    if workspace is not None:
+        import torch
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.is_contiguous()):
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
     return o
 
 
-def solve_tri(T, B, C=None, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None):
+def workspace_bytes(shape, prec=TT_FP64):
+    """Device bytes that one single-problem solve_tri / solve_general /
+    solve_backward call of this shape and precision needs at most
+    (tt_workspace_bytes); pass a CUDA tensor of at least this size as
+    workspace= and the call allocates no device memory."""
+    return int(lib().tt_workspace_bytes(len(shape), _shape(shape), int(prec)))
+
+
+def solve_tri(T, B, C=None, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None,
+              workspace=None):
     """Solve sum_mu X x_mu T_mu = B (Laplace-like form, eq. (2.2)) or, with
     C given, the pair form sum_mu X x_1 C_1 .. x_mu T_mu .. x_d C_d = B.
     T, C: lists of n_mu x n_mu float64 CUDA tensors (T upper quasi-triangular,
     C upper triangular); B: float64 CUDA tensor of shape (n_1, ..., n_d).
     prec=TT_MP_FP32: FP32-MFMA updates with FP64 refinement (info, if a dict,
-    receives iterations and the last correction ratio)."""
+    receives iterations and the last correction ratio).  workspace: an
+    optional CUDA tensor of at least workspace_bytes(B.shape, prec) bytes
+    from which every device buffer of the call is carved."""
     import torch
     if X is None:
         X = torch.empty_like(B)
     tp = _ptr_array([_dev(t) for t in T])
     cp = _ptr_array([_dev(c) for c in C]) if C is not None else None
-    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream)
+    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream, workspace=workspace)
     rc = lib().solve_tri_tensor(B.dim(), _shape(B.shape), tp, cp, _dev(B), _dev(X), ctypes.byref(o))
     if info is not None:
         info.update(iterations=int(o.info[0]), ratio=o.info[1], host_seconds=o.info[2])
@@ -152,7 +172,8 @@ def _host_mats(A):
     return mats, _ptr_array([m.ctypes.data for m in mats])
 
 
-def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None):
+def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, stream=None, info=None,
+                  workspace=None):
     """Algorithm 1: solve sum_mu X x_mu A_mu = B for dense A_mu given as HOST
     (numpy) n_mu x n_mu arrays; B: float64 CUDA tensor.  Host Schur, then
     transforms and the triangular solve on the GPU."""
@@ -160,7 +181,7 @@ def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, st
     if X is None:
         X = torch.empty_like(B)
     mats, ap = _host_mats(A)
-    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream)
+    o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter, stream=stream, workspace=workspace)
     rc = lib().solve_general_tensor(B.dim(), _shape(B.shape), ap, _dev(B), _dev(X), ctypes.byref(o))
     if info is not None:
         info.update(iterations=int(o.info[0]), ratio=o.info[1], host_seconds=o.info[2])
@@ -168,7 +189,7 @@ def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, st
     return X
 
 
-def solve_backward(T, X, G, dB=None, grads=True, dense_grad=False, nmin=0, stream=None):
+def solve_backward(T, X, G, dB=None, grads=True, dense_grad=False, nmin=0, stream=None, workspace=None):
     """Adjoint of solve_tri for L with dL/dX = G: returns (dB, dT) with
     dB = Lam solving sum_mu Lam x_mu T_mu^T = G and dT[mu] = -Lam_(mu) X_(mu)^T
     (masked to the pattern of T[mu] unless dense_grad); dT is None if not grads."""
@@ -178,7 +199,7 @@ def solve_backward(T, X, G, dB=None, grads=True, dense_grad=False, nmin=0, strea
     tp = _ptr_array([_dev(t) for t in T])
     dT = [torch.empty_like(t) for t in T] if grads else None
     dtp = _ptr_array([_dev(t) for t in dT]) if grads else None
-    o = _opts(nmin=nmin, stream=stream)
+    o = _opts(nmin=nmin, stream=stream, workspace=workspace)
     _check(lib().solve_backward(G.dim(), _shape(G.shape), tp, ctypes.c_void_p(_dev(X)) if grads else None,
                                 _dev(G), _dev(dB), dtp, int(bool(dense_grad)), ctypes.byref(o)))
     return dB, dT
@@ -384,12 +405,50 @@ def schedule_info(T_host, shape, nmin=0):
     """Host-only: statistics and dependency check of the solve schedule for
     coefficients given as numpy arrays (no GPU needed)."""
     Th = [np.ascontiguousarray(t, dtype=np.float64) for t in T_host]
-    out = (ctypes.c_double * 13)()
+    out = (ctypes.c_double * 14)()
     _check(lib().tt_schedule_info(len(shape), _shape(shape), _ptr_array([t.ctypes.data for t in Th]),
                                   int(nmin), out))
     keys = ["flops", "flops_leaf", "flops_update", "waves", "leaves", "tasks", "items", "launches",
-            "bmax0", "bmax1", "bmax2", "bmax3", "dependency_violation"]
+            "bmax0", "bmax1", "bmax2", "bmax3", "dependency_violation", "plan_bytes"]
     return dict(zip(keys, list(out)))
+
+
+class _PlanCache:
+    """Reusable plans keyed by the coefficient tensors themselves: an entry
+    holds weak references to its T tensors and their in-place versions, so
+    it is used only while the same tensors, unmodified, are passed again
+    (a freed tensor whose memory is reused never matches)."""
+
+    def __init__(self, cap=8):
+        self.cap = cap
+        self.entries = []  # (refs, versions, shape, trans, plan), newest last
+        self.misses = 0    # plans built so far
+
+    def get(self, T, shape, trans):
+        import weakref
+        shape = tuple(int(x) for x in shape)
+        vers = tuple(t._version for t in T)
+        for i, (refs, v, shp, tr, plan) in enumerate(self.entries):
+            if tr == trans and shp == shape and v == vers and len(refs) == len(T) and \
+                    all(r() is t for r, t in zip(refs, T)):
+                self.entries.append(self.entries.pop(i))
+                return plan
+        plan = Plan(list(T), shape, trans=trans)
+        self.misses += 1
+        self.entries.append(([weakref.ref(t) for t in T], vers, shape, trans, plan))
+        while len(self.entries) > self.cap:
+            self.entries.pop(0)[4].close()
+        return plan
+
+
+_plans = None
+
+
+def _plan_cache():
+    global _plans
+    if _plans is None:
+        _plans = _PlanCache()
+    return _plans
 
 
 def _autograd_class():
@@ -398,11 +457,16 @@ def _autograd_class():
     class TriTensorSolve(torch.autograd.Function):
         """X = solve_tri(T, B) with gradients: dL/dB = Lam (adjoint solve)
         and dL/dT_mu = -Lam_(mu) X_(mu)^T masked to the pattern of T_mu.
-        Usage: X = TriTensorSolve.apply(B, T_1, ..., T_d)."""
+        Usage: X = TriTensorSolve.apply(B, T_1, ..., T_d).  The forward plan
+        and the adjoint plan (T_mu^T, reversed order) are built once per set
+        of coefficient tensors and reused while those tensors are unchanged."""
 
         @staticmethod
         def forward(ctx, B, *T):
-            X = solve_tri(list(T), B.contiguous())
+            T = [t.contiguous() for t in T]
+            plan = _plan_cache().get(T, B.shape, False)
+            X = plan.solve(B.contiguous())
+            plan.status()
             ctx.save_for_backward(X, *T)
             return X
 
@@ -410,9 +474,10 @@ def _autograd_class():
         def backward(ctx, G):
             X, *T = ctx.saved_tensors
             need_T = any(ctx.needs_input_grad[1:])
-            dB, dT = solve_backward(T, X, G.contiguous(), grads=need_T)
-            if not need_T:
-                dT = [None] * len(T)
+            planb = _plan_cache().get(T, X.shape, True)
+            dB = planb.solve(G.contiguous())
+            dT = planb.coefficient_grads(T, X, dB) if need_T else [None] * len(T)
+            planb.status()
             return (dB,) + tuple(dT)
 
     return TriTensorSolve

@@ -84,7 +84,17 @@ struct tt_plan_s {
     UpdDesc* d_tasks = nullptr;
     WorkItem* d_items = nullptr;
     int* d_status = nullptr;
-    std::vector<void*> owned;  // T copies, block-start arrays, accumulators
+    std::vector<void*> owned;  // device buffers allocated by the library
+    // caller-provided device workspace (tt_opts::workspace): every device
+    // buffer is carved from it instead of allocated; uploads are then ordered
+    // on up_stream (the stream of the options)
+    char* ws_base = nullptr;
+    size_t ws_cap = 0, ws_used = 0;
+    hipStream_t up_stream = nullptr;
+    // all launches on the caller's stream (no side stream, no events)
+    bool serial_only = false;
+    std::vector<char> image;     // host images of uploaded tables
+    std::vector<ProbDesc> pdesc;
     hipStream_t side = nullptr;  // stream of the update launches
     std::vector<hipEvent_t> evL, evU;
     hipEvent_t ev_start = nullptr;
@@ -104,7 +114,7 @@ struct tt_plan_s {
     // the end of its last upload
     double* gW = nullptr;
     size_t gW_size = 0;
-    GramJob* gJobsHost = nullptr;
+    std::vector<GramJob> gJobsHost;
     GramJob* gJobsDev = nullptr;
     int gJobsCap = 0;
     hipEvent_t gJobsEv = nullptr;
@@ -115,7 +125,7 @@ struct tt_plan_s {
     std::vector<double*> Adev;   // dense A_mu (device) for the FP64 residual
     double* R = nullptr;         // residual / correction tensor
     double* part = nullptr;      // norm partial sums (device)
-    double* part_host = nullptr; // pinned host copy
+    std::vector<double> part_host;  // host copy
     double last_info[2] = {0, 0};
     // the solve recorded as a HIP graph (tt_plan_solve_graph) and the
     // (B, X, stream) it was recorded for
@@ -137,20 +147,12 @@ struct tt_plan_s {
         for (hipEvent_t e : evU) (void)hipEventDestroy(e);
         if (ev_start) (void)hipEventDestroy(ev_start);
         if (side) (void)hipStreamDestroy(side);
+        if (gJobsEv) (void)hipEventSynchronize(gJobsEv);
+        // uploads into a caller workspace are asynchronous on up_stream and
+        // read host vectors of this plan
+        if (ws_base) (void)hipStreamSynchronize(up_stream);
         for (void* p : owned) (void)hipFree(p);
-        if (gW) (void)hipFree(gW);
-        if (gJobsDev) (void)hipFree(gJobsDev);
-        if (gJobsHost) (void)hipHostFree(gJobsHost);
         if (gJobsEv) (void)hipEventDestroy(gJobsEv);
-        if (d_probs) (void)hipFree(d_probs);
-        if (d_leaves) (void)hipFree(d_leaves);
-        if (d_shapes) (void)hipFree(d_shapes);
-        if (d_ents) (void)hipFree(d_ents);
-        if (d_hoffs) (void)hipFree(d_hoffs);
-        if (d_tasks) (void)hipFree(d_tasks);
-        if (d_items) (void)hipFree(d_items);
-        if (d_status) (void)hipFree(d_status);
-        if (part_host) (void)hipHostFree(part_host);
     }
 };
 
@@ -220,30 +222,100 @@ int fetch_coefficients(const double* const* T, int trans, HostProblem& hp) {
     return TT_OK;
 }
 
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device buffer of a plan: carved from the caller's workspace when the plan
+// has one (256-byte aligned, TT_ENOMEM with the needed size when it runs
+// out), else allocated and owned by the plan.
+int dev_alloc(tt_plan_s* P, size_t bytes, void** out, const char* what) {
+    *out = nullptr;
+    bytes = align256(std::max<size_t>(bytes, 1));
+    if (P->ws_base) {
+        if (P->ws_used + bytes > P->ws_cap)
+            return fail(TT_ENOMEM, std::string("workspace too small for ") + what + ": needs at least " +
+                                       std::to_string(P->ws_used + bytes) + " bytes, has " +
+                                       std::to_string(P->ws_cap));
+        *out = P->ws_base + P->ws_used;
+        P->ws_used += bytes;
+        return TT_OK;
+    }
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        *out = nullptr;
+        return fail(TT_ENOMEM, std::string("hipMalloc failed (") + what + ")");
+    }
+    P->owned.push_back(*out);
+    return TT_OK;
+}
+
+// Host -> device copy of plan data: ordered on the options' stream when the
+// memory is the caller's workspace (earlier work there may still use it),
+// else synchronous.
+int to_device(tt_plan_s* P, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return TT_OK;
+    if (P->ws_base) {
+        TT_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, P->up_stream));
+    } else {
+        TT_HIP_CHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    }
+    return TT_OK;
+}
+
 template <typename V>
-int upload(const std::vector<V>& v, V** dst) {
+int upload(tt_plan_s* P, const std::vector<V>& v, V** dst) {
     *dst = nullptr;
     if (v.empty()) return TT_OK;
-    if (hipMalloc((void**)dst, sizeof(V) * v.size()) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-    TT_HIP_CHECK(hipMemcpy(*dst, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice));
-    return TT_OK;
+    int rc = dev_alloc(P, sizeof(V) * v.size(), (void**)dst, "plan tables");
+    if (rc) return rc;
+    return to_device(P, *dst, v.data(), sizeof(V) * v.size());
 }
 
 int upload_matrix(tt_plan_s* P, const std::vector<double>& m, double** out) {
-    *out = nullptr;
-    if (hipMalloc((void**)out, sizeof(double) * std::max<size_t>(1, m.size())) != hipSuccess)
-        return fail(TT_ENOMEM, "hipMalloc failed");
-    P->owned.push_back(*out);
-    if (!m.empty()) TT_HIP_CHECK(hipMemcpy(*out, m.data(), sizeof(double) * m.size(), hipMemcpyHostToDevice));
-    return TT_OK;
+    int rc = dev_alloc(P, sizeof(double) * m.size(), (void**)out, "coefficient matrix");
+    if (rc) return rc;
+    return to_device(P, *out, m.data(), sizeof(double) * m.size());
 }
 
 int alloc_tensor(tt_plan_s* P, int64_t N, double** out) {
-    *out = nullptr;
-    if (hipMalloc((void**)out, sizeof(double) * (size_t)std::max<int64_t>(1, N)) != hipSuccess)
-        return fail(TT_ENOMEM, "hipMalloc failed (workspace tensor)");
-    P->owned.push_back(*out);
-    return TT_OK;
+    return dev_alloc(P, sizeof(double) * (size_t)std::max<int64_t>(1, N), (void**)out, "workspace tensor");
+}
+
+// Set while a plan is built that runs every launch on the caller's stream
+// (no side stream and no events).
+thread_local bool t_serial_plan = false;
+
+// Take the options' workspace (if any) for the plan's device buffers.
+void adopt_workspace(tt_plan_s* P, const tt_opts* opts) {
+    P->serial_only = t_serial_plan;
+    if (!opts || !opts->workspace) return;
+    P->ws_base = (char*)opts->workspace;
+    P->ws_cap = opts->workspace_bytes;
+    P->ws_used = 0;
+    // keep the carved buffers 256-byte aligned whatever the base
+    const size_t mis = (size_t)((uintptr_t)P->ws_base & 255);
+    if (mis) {
+        const size_t skip = 256 - mis;
+        P->ws_base += skip;
+        P->ws_cap = P->ws_cap > skip ? P->ws_cap - skip : 0;
+    }
+    P->up_stream = (hipStream_t)opts->stream;
+}
+
+// Device bytes finish_plan takes for a built schedule (tables, coefficient
+// copies, block starts, accumulators, status word), as dev_alloc rounds them.
+size_t plan_table_bytes(const Schedule& s) {
+    auto al = align256;
+    size_t cbytes = 0, abytes = 0;
+    for (const HostProblem& hp : s.probs)
+        for (int mu = 0; mu < s.D; ++mu) {
+            cbytes += al(sizeof(double) * std::max<size_t>(1, hp.T[mu].size()));
+            cbytes += al(sizeof(int32_t) * hp.bst[mu].size());
+            if (mu >= 1 && hp.N > 0) abytes += al(sizeof(double) * (size_t)hp.N);
+        }
+    auto tb = [&](size_t n, size_t sz) { return n ? al(n * sz) : 0; };
+    return al(std::max<size_t>(cbytes, 1)) + (abytes ? al(abytes) : 0) + tb(s.probs.size(), sizeof(ProbDesc)) +
+           tb(s.leaves.size(), sizeof(LeafDesc)) + tb(s.shapes.size(), sizeof(LeafShape)) +
+           tb(s.ents.size(), sizeof(uint16_t)) + tb(s.hoffs.size(), sizeof(int32_t)) +
+           tb(s.tasks.size(), sizeof(UpdDesc)) + tb(s.items.size(), sizeof(WorkItem)) + al(sizeof(int) * 4);
 }
 
 int finish_plan(tt_plan_s* P, int nmin) {
@@ -255,7 +327,7 @@ int finish_plan(tt_plan_s* P, int nmin) {
     // (filled by one copy from a packed host image) and one for the update
     // accumulators: a batched plan makes two allocations instead of several
     // per problem and mode.
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    auto al = align256;
     size_t cbytes = 0, abytes = 0;
     for (const HostProblem& hp : s.probs)
         for (int mu = 0; mu < s.D; ++mu) {
@@ -266,13 +338,8 @@ int finish_plan(tt_plan_s* P, int nmin) {
         }
     char* dc = nullptr;
     char* da = nullptr;
-    if (hipMalloc((void**)&dc, std::max<size_t>(cbytes, 256)) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-    P->owned.push_back(dc);
-    if (abytes > 0) {
-        if (hipMalloc((void**)&da, abytes) != hipSuccess)
-            return fail(TT_ENOMEM, "hipMalloc failed (update accumulators)");
-        P->owned.push_back(da);
-    }
+    if ((rc = dev_alloc(P, cbytes, (void**)&dc, "coefficients"))) return rc;
+    if (abytes > 0 && (rc = dev_alloc(P, abytes, (void**)&da, "update accumulators"))) return rc;
     std::vector<char> image(cbytes, 0);
     std::vector<ProbDesc> pd(s.probs.size());
     size_t co = 0, ao = 0;
@@ -297,16 +364,20 @@ int finish_plan(tt_plan_s* P, int nmin) {
             }
         }
     }
-    if (cbytes > 0) TT_HIP_CHECK(hipMemcpy(dc, image.data(), cbytes, hipMemcpyHostToDevice));
-    if ((rc = upload(pd, &P->d_probs))) return rc;
-    if ((rc = upload(s.leaves, &P->d_leaves))) return rc;
-    if ((rc = upload(s.shapes, &P->d_shapes))) return rc;
-    if ((rc = upload(s.ents, &P->d_ents))) return rc;
-    if ((rc = upload(s.hoffs, &P->d_hoffs))) return rc;
-    if ((rc = upload(s.tasks, &P->d_tasks))) return rc;
-    if ((rc = upload(s.items, &P->d_items))) return rc;
-    if (hipMalloc((void**)&P->d_status, sizeof(int) * 4) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
-    TT_HIP_CHECK(hipMemset(P->d_status, 0, sizeof(int) * 4));
+    P->image = std::move(image);  // kept until the plan is destroyed (asynchronous upload)
+    if ((rc = to_device(P, dc, P->image.data(), cbytes))) return rc;
+    P->pdesc = std::move(pd);
+    if ((rc = upload(P, P->pdesc, &P->d_probs))) return rc;
+    if ((rc = upload(P, s.leaves, &P->d_leaves))) return rc;
+    if ((rc = upload(P, s.shapes, &P->d_shapes))) return rc;
+    if ((rc = upload(P, s.ents, &P->d_ents))) return rc;
+    if ((rc = upload(P, s.hoffs, &P->d_hoffs))) return rc;
+    if ((rc = upload(P, s.tasks, &P->d_tasks))) return rc;
+    if ((rc = upload(P, s.items, &P->d_items))) return rc;
+    // status word: cleared by every solve before its first launch
+    if ((rc = dev_alloc(P, sizeof(int) * 4, (void**)&P->d_status, "status word"))) return rc;
+    TT_HIP_CHECK(launch_zero_int(P->d_status, 4, P->up_stream));
+    if (P->serial_only) return TT_OK;
     TT_HIP_CHECK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
     P->evL.resize(s.waves.size());
     P->evU.resize(s.waves.size());
@@ -346,6 +417,19 @@ struct ProfEvents {
 
 int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int lp = 0) {
     Schedule& s = P->sched;
+    if (P->serial_only) {
+        // one stream: wave k's leaves, then the updates ready after them
+        const int leaf_lds = leaf_lds_bytes(s.D, s.bmax, s.maxtup, s.maxcpl, s.maxH);
+        for (const Wave& wv : s.waves) {
+            TT_HIP_CHECK(launch_leaf(s.D, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
+                                     P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH,
+                                     st));
+            TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp,
+                                       leaf_lds, st));
+        }
+        P->last_stream = st;
+        return TT_OK;
+    }
     TT_HIP_CHECK(hipEventRecord(P->ev_start, st));
     TT_HIP_CHECK(hipStreamWaitEvent(P->side, P->ev_start, 0));
     const size_t W = s.waves.size();
@@ -504,7 +588,7 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
         if ((rc = run_pipeline(P, P->R, P->R, 1, st))) return rc;
         TT_HIP_CHECK(launch_axpy(X, P->R, 1.0, hp.N, st));
         TT_HIP_CHECK(launch_sumsq2(P->R, X, hp.N, P->part, st));
-        TT_HIP_CHECK(hipMemcpyAsync(P->part_host, P->part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+        TT_HIP_CHECK(hipMemcpyAsync(P->part_host.data(), P->part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
         TT_HIP_CHECK(hipStreamSynchronize(st));
         double dd = 0, xx = 0;
         for (int b = 0; b < nb; ++b) {
@@ -534,11 +618,8 @@ int setup_refinement(tt_plan_s* P, const std::vector<std::vector<double>>& A, co
     for (size_t mu = 0; mu < A.size(); ++mu)
         if ((rc = upload_matrix(P, A[mu], &P->Adev[mu]))) return rc;
     if ((rc = alloc_tensor(P, hp.N, &P->R))) return rc;
-    if (hipMalloc((void**)&P->part, sizeof(double) * 2 * sumsq_blocks()) != hipSuccess)
-        return fail(TT_ENOMEM, "hipMalloc failed");
-    P->owned.push_back(P->part);
-    if (hipHostMalloc((void**)&P->part_host, sizeof(double) * 2 * sumsq_blocks(), 0) != hipSuccess)
-        return fail(TT_ENOMEM, "hipHostMalloc failed");
+    if ((rc = dev_alloc(P, sizeof(double) * 2 * sumsq_blocks(), (void**)&P->part, "norm partial sums"))) return rc;
+    P->part_host.assign((size_t)2 * sumsq_blocks(), 0.0);
     return TT_OK;
 }
 
@@ -567,7 +648,93 @@ int plan_begin(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::vec
 
 }  // namespace
 
+// Upper bound of the device bytes of one single-problem plan and call (see
+// tt_workspace_bytes).  Every term mirrors an allocation of this file with
+// the counts the planner can produce for ANY 2x2-block pattern:
+//   blocks per mode  m <= ceil(n / b) + 1 (near-equal split, one extra block
+//                    when a moved boundary leaves a block over b rows; the
+//                    full-block split is taken only when it has no more);
+//   leaf edge        <= b + 1 (a near-equal block of ceil(n/m) <= b rows
+//                       grows by one when its first boundary moves down
+//                       past a 2x2 block; a move up is taken only when the
+//                       block stays within b; full blocks have <= b rows);
+//   tasks            <= 2 D leaves (types (1) and (2) per block and mode);
+//   update tiles     <= tiles of the tasks' (M, P) + 8 padding items a wave,
+//                       where per pencil and mode the targets of one tree
+//                       level cover at most n rows, for both task types;
+//   tuple shapes     distinct tuple counts per mode <= min(m, leaf edge).
+size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
+    if (d < 1 || d > 4 || !n) return 0;
+    const int D = (d == 4) ? 4 : 3;
+    const int b = (D >= 4) ? 8 : 16;  // default leaf edge (build_schedule)
+    int64_t nn[kMaxD] = {1, 1, 1, 1};
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] < 0) return 0;
+        nn[D - d + mu] = n[mu];
+    }
+    auto al = align256;
+    double N = 1;
+    for (int mu = 0; mu < D; ++mu) N *= (double)nn[mu];
+    size_t coef = 0, mats = 0;
+    double L = 1, S = 1, ents = 1, tiles_idx = 0, W = 1, lev_rows = 0, nmax = 1;
+    int64_t m[kMaxD], bm[kMaxD];
+    for (int mu = 0; mu < D; ++mu) {
+        const int64_t nm = nn[mu];
+        m[mu] = (nm == 0) ? 0 : std::min<int64_t>(nm, (nm + b - 1) / b + 1);
+        bm[mu] = std::max<int64_t>(1, std::min<int64_t>(nm, b + 1));
+        coef += al(sizeof(double) * (size_t)std::max<int64_t>(1, nm * nm)) + al(sizeof(int32_t) * (size_t)(m[mu] + 1));
+        mats += al(sizeof(double) * (size_t)std::max<int64_t>(1, nm * nm));
+        L *= (double)m[mu];
+        W += (double)std::max<int64_t>(0, m[mu] - 1);
+        nmax = std::max(nmax, (double)nm);
+        const int64_t distinct = std::min<int64_t>(m[mu], bm[mu]);
+        S *= (double)std::max<int64_t>(1, distinct);
+        double tsum = 0;  // sum of the largest `distinct` tuple counts <= bm
+        for (int64_t k = 0; k < distinct; ++k) tsum += (double)(bm[mu] - k);
+        ents *= std::max(1.0, tsum);
+    }
+    if (N == 0) return 4096;
+    (void)tiles_idx;
+    double Pmax = 1;
+    for (int mu = 0; mu < D - 1; ++mu) Pmax *= (double)bm[mu];
+    const double tasks = 2.0 * D * L;
+    for (int mu = 0; mu < D; ++mu) {
+        const double levels = std::log2(std::max<double>(2.0, (double)m[mu])) + 2.0;
+        lev_rows += 2.0 * levels * (double)nn[mu] * L / std::max<double>(1.0, (double)m[mu]) / kTile;
+    }
+    const double items = std::ceil(Pmax / kTile) * (lev_rows + tasks) + 8.0 * W;
+    double Hmax = 1;
+    for (int mu = 0; mu < D; ++mu) Hmax += (double)bm[mu];
+    double bytes = (double)coef + al(sizeof(ProbDesc)) + L * sizeof(LeafDesc) + S * sizeof(LeafShape) +
+                   ents * sizeof(uint16_t) + S * (Hmax + 1) * sizeof(int32_t) + tasks * sizeof(UpdDesc) +
+                   items * sizeof(WorkItem) + 9 * 256.0;  // alignment of the tables, status word
+    bytes += (double)(D - 1) * (double)al((size_t)(8.0 * N));  // update accumulators
+    // the largest of the extras: dense pipeline (pre, post, one tensor)
+    // with refinement (dense A, residual tensor, norm partial sums), the
+    // pair form (pre, one tensor), the adjoint's gradient workspace
+    const double tensor = (double)al((size_t)(8.0 * N));
+    double general = 2.0 * (double)mats + tensor;
+    if (prec != TT_FP64) general += (double)mats + tensor + al(sizeof(double) * 2 * (size_t)sumsq_blocks());
+    const double pair = (double)mats + tensor;
+    double gtiles = 0;
+    for (int mu = 0; mu < D; ++mu) gtiles += std::pow(std::ceil((double)nn[mu] / kGramTile), 2.0);
+    const double want = std::max(1.0, std::floor(4096.0 / std::max(1.0, gtiles)));
+    double grads = al(sizeof(GramJob) * (size_t)D);
+    for (int mu = 0; mu < D; ++mu) {
+        if (nn[mu] == 0) continue;
+        const double K = N / (double)nn[mu];
+        const double ns = std::min(want, std::max(1.0, std::floor(K / 512.0)));
+        grads += ns * (double)nn[mu] * (double)nn[mu] * 8.0;
+    }
+    grads = (double)al((size_t)grads);
+    bytes += std::max(std::max(general, pair), grads);
+    (void)nmax;
+    return (size_t)std::ceil(bytes) + 4096;
+}
+
 extern "C" {
+
+size_t tt_workspace_bytes(int d, const int64_t* n, int prec) { return plan_bound_bytes(d, n, prec); }
 
 int tt_opts_default(tt_opts* o) {
     if (!o) return fail(TT_EINVAL, "opts is NULL");
@@ -603,6 +770,7 @@ int tt_plan_create_batched(tt_plan* out, int count, const int* d, const int64_t*
         return fail(TT_EINVAL, "batched plans are FP64 only (mixed precision: tt_plan_create, tt_plan_create_general)");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
     P->trans = trans ? 1 : 0;
     P->count = count;
     const int D = internal_order(d, count);
@@ -705,6 +873,7 @@ int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T
     if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "mixed precision is not supported for the pair form");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
     HostProblem probe;
     int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
     if (rc) return rc;
@@ -733,6 +902,7 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n, const double* 
     if (!A_host) return fail(TT_EINVAL, "coefficient array is NULL");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
     HostProblem probe;
     int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
     if (rc) return rc;
@@ -794,6 +964,7 @@ int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const dou
     if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "mixed precision is not supported for the pair form");
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
     HostProblem probe;
     int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
     if (rc) return rc;
@@ -1135,13 +1306,11 @@ static int grads_batched(tt_plan_s* P, const double* const* const* T, const doub
         ws += (size_t)ns * (size_t)J.n * (size_t)J.n;
     }
     if (ws > P->gW_size) {
-        if (P->gW) {
-            TT_HIP_CHECK(hipStreamSynchronize(st));
-            TT_HIP_CHECK(hipFree(P->gW));
-            P->gW = nullptr;
-            P->gW_size = 0;
-        }
-        if (hipMalloc((void**)&P->gW, sizeof(double) * ws) != hipSuccess) return fail(TT_ENOMEM, "hipMalloc failed");
+        // grown only when a call needs more: the old buffer stays with the
+        // plan (work already enqueued may still read it), so no
+        // synchronisation is needed here
+        int rc2 = dev_alloc(P, sizeof(double) * ws, (void**)&P->gW, "gradient split-K workspace");
+        if (rc2) return rc2;
         P->gW_size = ws;
     }
     for (size_t j = 0; j < jobs.size(); ++j) jobs[j].W = P->gW + woff[j];
@@ -1149,21 +1318,12 @@ static int grads_batched(tt_plan_s* P, const double* const* const* T, const doub
     if (!P->gJobsEv) TT_HIP_CHECK(hipEventCreateWithFlags(&P->gJobsEv, hipEventDisableTiming));
     TT_HIP_CHECK(hipEventSynchronize(P->gJobsEv));  // the previous upload has read the staging buffer
     if (nj > P->gJobsCap) {
-        if (P->gJobsDev) {
-            TT_HIP_CHECK(hipStreamSynchronize(st));
-            TT_HIP_CHECK(hipFree(P->gJobsDev));
-            P->gJobsDev = nullptr;
-        }
-        if (P->gJobsHost) TT_HIP_CHECK(hipHostFree(P->gJobsHost));
-        P->gJobsHost = nullptr;
-        P->gJobsCap = 0;
-        if (hipHostMalloc((void**)&P->gJobsHost, sizeof(GramJob) * nj, 0) != hipSuccess ||
-            hipMalloc((void**)&P->gJobsDev, sizeof(GramJob) * nj) != hipSuccess)
-            return fail(TT_ENOMEM, "allocation of the gradient job table failed");
+        int rc2 = dev_alloc(P, sizeof(GramJob) * nj, (void**)&P->gJobsDev, "gradient job table");
+        if (rc2) return rc2;
         P->gJobsCap = nj;
     }
-    std::memcpy(P->gJobsHost, jobs.data(), sizeof(GramJob) * nj);
-    TT_HIP_CHECK(hipMemcpyAsync(P->gJobsDev, P->gJobsHost, sizeof(GramJob) * nj, hipMemcpyHostToDevice, st));
+    P->gJobsHost = jobs;
+    TT_HIP_CHECK(hipMemcpyAsync(P->gJobsDev, P->gJobsHost.data(), sizeof(GramJob) * nj, hipMemcpyHostToDevice, st));
     TT_HIP_CHECK(hipEventRecord(P->gJobsEv, st));
     TT_HIP_CHECK(launch_gram_batched(P->gJobsDev, nj, wg, el, -1.0, st));
     return TT_OK;
@@ -1259,6 +1419,7 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
     out[6] = (double)st.items;
     out[7] = (double)st.launches;  // two per wave (leaf + update)
     for (int mu = 0; mu < 4; ++mu) out[8 + mu] = st.bmax[mu];
+    out[13] = (double)plan_table_bytes(s);
     // Dependency check: replay the waves.  In wave k the updates (ready
     // after wave k-1) run concurrently with the leaves of wave k, so an update
     // must read only blocks solved before wave k and write only blocks of

@@ -91,3 +91,43 @@ def test_plan_entry_points_reject_null_plan():
     for fn in (L.tt_plan_solve, L.tt_plan_solve_graph):
         assert fn(null, null, null, null) == tt.TT_EINVAL
         assert b"NULL" in L.tt_last_error()
+
+
+def _dense_bumps(n, g):
+    """Upper quasi-triangular n x n with a 2x2 block at every even row: the
+    most 2x2 blocks a real Schur form can hold."""
+    T = np.triu(g.standard_normal((n, n)) / np.sqrt(n))
+    for i in range(0, n - 1, 2):
+        a, b = 1.0 + g.random(), 0.1 + 0.4 * g.random()
+        T[i, i] = T[i + 1, i + 1] = a
+        T[i, i + 1], T[i + 1, i] = b, -b
+    if n % 2:
+        T[n - 1, n - 1] = 1.0 + g.random()
+    return T
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (512, 512, 512), (37, 20, 45), (96, 96, 96, 96),
+                                   (1024, 1024, 8, 8), (5, 7, 3), (64,), (50, 70), (200, 150, 180),
+                                   (1, 1, 1), (768, 40, 3), (19, 23, 29, 17), (17, 16, 15)])
+@pytest.mark.parametrize("bumps", ["every8", "aligned", "random", "none", "dense"])
+def test_workspace_bound_covers_every_pattern(shape, bumps):
+    """tt_workspace_bytes is a bound over every 2x2-block pattern: the plan's
+    tables, coefficient copies and accumulators (exact, from the host
+    schedule) plus the largest extra tensor of any call kind fit in it."""
+    if bumps == "dense":
+        g = np.random.default_rng(11)
+        T = [_dense_bumps(n, g) for n in shape]
+    else:
+        T = ti.laplace_tri(shape, seed=3, bumps=bumps)["T"]
+    info = tt.schedule_info(T, shape)
+    N = int(np.prod(shape))
+    for prec in (tt.TT_FP64, tt.TT_MP_FP32):
+        bound = tt.workspace_bytes(shape, prec)
+        assert bound >= info["plan_bytes"] + 8 * N, (bound, info["plan_bytes"])
+    assert tt.workspace_bytes(shape, tt.TT_MP_FP32) >= tt.workspace_bytes(shape, tt.TT_FP64)
+
+
+def test_workspace_bytes_rejects_bad_shapes():
+    assert tt.workspace_bytes((4, 4, 4, 4, 4)) == 0
+    assert tt.workspace_bytes((4, -1, 4)) == 0
+    assert tt.workspace_bytes((0, 5, 5)) > 0
