@@ -127,6 +127,30 @@ int solve_tri_tensor(int d, const int64_t* n, const double* const* T,
                      tt_opts* opts);
 
 /* ---------------------------------------------------------------------------
+ * solve_tri_tensor_noalloc - solve_tri_tensor for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same arguments, kernels and
+ * result, but every device buffer of the call (plan tables, coefficient
+ * copies, update accumulators, pair-form transforms, status word) lives in
+ * a fixed scratch array of 64 MiB that the library holds on each GPU it
+ * runs on until the process ends; no hipMalloc/hipFree or allocating
+ * library routine is called, and every launch goes to opts->stream (no
+ * side stream, no events).  Enough for a d = 3 problem of about 150^3
+ * elements (two accumulators of 8 N bytes plus tables).
+ *   Argument meaning, layout and ownership: as solve_tri_tensor.
+ *   opts->prec must be TT_FP64; opts->workspace is ignored.
+ *   Calls on one GPU share its scratch array: calls that overlap in time on
+ *   one GPU (other host threads, or streams not ordered with each other)
+ *   race and give wrong results.  The array keeps the last call's contents;
+ *   the call itself clears what must start at zero (the status word).
+ * Errors: as solve_tri_tensor; TT_EINVAL also when the problem needs more
+ * than the scratch array holds (the message gives the size needed).
+ * ------------------------------------------------------------------------- */
+int solve_tri_tensor_noalloc(int d, const int64_t* n, const double* const* T,
+                             const double* const* C, const double* B, double* X,
+                             tt_opts* opts);
+
+/* ---------------------------------------------------------------------------
  * solve_general_tensor - Algorithm 1 of the paper for dense coefficients:
  * real Schur decomposition A_mu = U_mu T_mu U_mu^T on the host (Hessenberg
  * reduction + Francis double-shift QR), B~ = B x_1 U_1^T ... x_d U_d^T on the

@@ -46,7 +46,7 @@ SYMBOLS = [
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
-    "tt_copy_device", "tt_workspace_bytes",
+    "tt_copy_device", "tt_workspace_bytes", "solve_tri_tensor_noalloc",
 ]
 
 
@@ -64,6 +64,7 @@ def lib():
         L.tt_workspace_bytes.argtypes = [ctypes.c_int, i64p, ctypes.c_int]
         L.tt_workspace_bytes.restype = ctypes.c_size_t
         L.solve_tri_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_tri_tensor_noalloc.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_general_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_backward.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts)]
         L.solve_tri_tensor_batched.argtypes = [ctypes.c_int, ip, vp, vp, vp, vp, ctypes.POINTER(Opts)]
@@ -164,6 +165,17 @@ def solve_tri(T, B, C=None, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10
     if info is not None:
         info.update(iterations=int(o.info[0]), ratio=o.info[1], host_seconds=o.info[2])
     _check(rc)
+    return X
+
+
+def solve_tri_noalloc(T, B, X, C=None, nmin=0, stream=None):
+    """solve_tri through solve_tri_tensor_noalloc: no device allocation in
+    the library (its buffers live in a fixed 64 MiB scratch array per GPU);
+    X must be given (float64 CUDA tensor shaped like B)."""
+    tp = _ptr_array([_dev(t) for t in T])
+    cp = _ptr_array([_dev(c) for c in C]) if C is not None else None
+    o = _opts(nmin=nmin, stream=stream)
+    _check(lib().solve_tri_tensor_noalloc(B.dim(), _shape(B.shape), tp, cp, _dev(B), _dev(X), ctypes.byref(o)))
     return X
 
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -279,8 +280,8 @@ int alloc_tensor(tt_plan_s* P, int64_t N, double** out) {
     return dev_alloc(P, sizeof(double) * (size_t)std::max<int64_t>(1, N), (void**)out, "workspace tensor");
 }
 
-// Set while a plan is built that runs every launch on the caller's stream
-// (no side stream and no events).
+// Set while solve_tri_tensor_noalloc builds its plan: the plan then runs
+// every launch on the caller's stream (no side stream and no events).
 thread_local bool t_serial_plan = false;
 
 // Take the options' workspace (if any) for the plan's device buffers.
@@ -732,9 +733,65 @@ size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
     return (size_t)std::ceil(bytes) + 4096;
 }
 
+// Scratch of the allocation-free solve (solve_tri_tensor_noalloc): the
+// plan's tables, the update accumulators and the status word.  Each GPU
+// holds its own copy from module load until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+    int dev = 0;
+    TT_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        TT_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(TT_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TT_OK;
+}
+
 extern "C" {
 
 size_t tt_workspace_bytes(int d, const int64_t* n, int prec) { return plan_bound_bytes(d, n, prec); }
+
+int solve_tri_tensor_noalloc(int d, const int64_t* n, const double* const* T, const double* const* C,
+                             const double* B, double* X, tt_opts* opts) {
+    tt_opts o;
+    tt_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.prec != TT_FP64) return fail(TT_EINVAL, "the allocation-free solve is FP64 only");
+    void* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    o.workspace = ws;
+    o.workspace_bytes = kNoAllocScratchBytes;
+    tt_plan p = nullptr;
+    t_serial_plan = true;
+    rc = tt_plan_create(&p, d, n, T, C, 0, &o);
+    t_serial_plan = false;
+    if (rc == TT_ENOMEM)
+        return fail(TT_EINVAL, std::string("problem too large for the allocation-free solve (64 MiB of scratch): ") +
+                                   tt_last_error());
+    if (rc) return rc;
+    std::unique_ptr<tt_plan_s> guard(p);
+    rc = tt_plan_solve(p, B, X, o.stream);
+    if (opts) {
+        opts->info[0] = opts->info[1] = 0;
+        opts->info[2] = p->build_seconds;
+    }
+    if (rc) return rc;
+    return tt_plan_status(p);
+}
 
 int tt_opts_default(tt_opts* o) {
     if (!o) return fail(TT_EINVAL, "opts is NULL");
