@@ -11,7 +11,9 @@ Paper references (Chen & Kressner, arXiv 1905.09539):
   * Laplace-like equation sum_mu X x_mu A_mu = B: eq. (1.4) / (2.2);
     uniqueness iff no eigenvalue sum vanishes (Sec. 2);
   * real Schur (upper quasi-triangular) coefficients: Sec. 2, Algorithm 1;
-  * the two-matrices-per-mode family: Conclusions.
+  * the two-matrices-per-mode family: Conclusions;
+  * the second operator class X x_1 A_1 + X x_1 C x_2 A_2 .. x_d A_d:
+    eq. (1.5) / (3.1), Sec. 3 (Algorithms 4-6).
 
 Parity status per function (pins live in tests/test_oracle_pins.py):
   lap_solve ........ pinned (dense Kronecker LU, closed forms, Sylvester,
@@ -25,6 +27,12 @@ Parity status per function (pins live in tests/test_oracle_pins.py):
   flops_tri ........ pinned (closed form d (n-1) N for triangular cubes,
                      brute-force count of multiply-adds)
   dense_solve_with_factors  pinned (dense Kronecker LU of the dense A_mu)
+  gsylv_apply ...... pinned (dense Kronecker matrix of eq. (1.5))
+  gsylv_solve ...... pinned (dense Kronecker LU, SciPy Sylvester at d = 2,
+                     closed form for diagonal coefficients, eigenvector
+                     right-hand sides, the shifted Kronecker case eq. (1.6))
+  gsylv_dense_solve_with_factors  pinned (dense Kronecker LU of the dense
+                     second-class operator)
 """
 from __future__ import annotations
 
@@ -74,6 +82,9 @@ def lib():
             getattr(L, "oracle_pair_solve_direct" + sfx).restype = ctypes.c_int
             getattr(L, "oracle_pair_solve_reduced" + sfx).argtypes = [ctypes.c_int, i64p, dpp, dpp, vp, vp]
             getattr(L, "oracle_pair_solve_reduced" + sfx).restype = ctypes.c_int
+            getattr(L, "oracle_gsylv_apply" + sfx).argtypes = [ctypes.c_int, i64p, dpp, vp, vp, vp]
+            getattr(L, "oracle_gsylv_solve_direct" + sfx).argtypes = [ctypes.c_int, i64p, dpp, vp, vp, vp]
+            getattr(L, "oracle_gsylv_solve_direct" + sfx).restype = ctypes.c_int
             getattr(L, "oracle_grad_T" + sfx).argtypes = [ctypes.c_int, i64p, ctypes.c_int, vp, vp, vp, vp, ctypes.c_int]
         L.oracle_flops_tri.argtypes = [ctypes.c_int, i64p, dpp]
         L.oracle_flops_tri.restype = ctypes.c_double
@@ -163,6 +174,49 @@ def pair_solve(A, C, B, method="reduced", precision="f64"):
     if rc:
         raise OracleError(_STATUS.get(rc, str(rc)))
     return X
+
+
+def gsylv_apply(A, C, X, precision="f64"):
+    """X x_1 A_1 + X x_1 C x_2 A_2 .. x_d A_d (second class, eq. (3.1));
+    A[0], C act on the first mode."""
+    X = _f64(X)
+    A = [_f64(a) for a in A]
+    C = _f64(C)
+    Y = np.empty_like(X)
+    getattr(lib(), "oracle_gsylv_apply" + _sfx(precision))(
+        X.ndim, _shape(X.shape), _ptrs(A), C.ctypes.data, X.ctypes.data, Y.ctypes.data)
+    return Y
+
+
+def gsylv_solve(A, C, B, precision="f64"):
+    """Unique X of the second class (eq. (3.1)) with upper quasi-triangular
+    A_mu and upper triangular C, by direct element-wise back-substitution
+    (O(N^2): small sizes)."""
+    B = _f64(B)
+    A = [_f64(a) for a in A]
+    C = _f64(C)
+    X = np.empty_like(B)
+    rc = getattr(lib(), "oracle_gsylv_solve_direct" + _sfx(precision))(
+        B.ndim, _shape(B.shape), _ptrs(A), C.ctypes.data, B.ctypes.data, X.ctypes.data)
+    if rc:
+        raise OracleError(_STATUS.get(rc, str(rc)))
+    return X
+
+
+def gsylv_dense_solve_with_factors(Q, S, T, Z, U, Tq, B, precision="f64"):
+    """X for the dense second class with known factors (Algorithm 4):
+    A_1 = Q S Z^T, C = Q T Z^T, A_mu = U_mu Tq_mu U_mu^T (mu >= 2):
+    B~ = B x_1 Q^T x_mu U_mu^T, X~ = gsylv_solve([S, Tq..], T, B~),
+    X = X~ x_1 Z x_mu U_mu."""
+    W = _f64(B)
+    W = mode_product(W, _f64(Q).T.copy(), 0, precision)
+    for mu, u in enumerate(U, start=1):
+        W = mode_product(W, _f64(u).T.copy(), mu, precision)
+    Xt = gsylv_solve([S] + list(Tq), T, W, precision=precision)
+    Xt = mode_product(Xt, _f64(Z), 0, precision)
+    for mu, u in enumerate(U, start=1):
+        Xt = mode_product(Xt, _f64(u), mu, precision)
+    return Xt
 
 
 def grad_T(T, Lam, X, mu, mask=True, precision="f64"):

@@ -12,6 +12,8 @@
  *   - the adjoint (transposed) solve by forward substitution;
  *   - the pair operator  sum_mu X x_1 C_1 .. x_mu A_mu .. x_d C_d  and its
  *     solve, both directly and through the C^{-1} reduction;
+ *   - the second operator class X x_1 A_1 + X x_1 C x_2 A_2 .. x_d A_d
+ *     (eq. 1.5 / 3.1) and its direct solve;
  *   - mu-mode products (Sec. 2) and the coefficient gradient -Lam_(mu) X_(mu)^T;
  *   - the flop count of the method.
  * Instantiated in double (_f64) and x87 long double (_ld).

@@ -394,6 +394,149 @@ int FN(oracle_pair_solve_reduced)(int d, const int64_t* n, const double* const* 
     return rc;
 }
 
+/* ------------------------------------------------------------------------
+ * Second operator class, eq. (1.5) / (3.1):
+ *   X x_1 A_1 + X x_1 C x_2 A_2 x_3 ... x_d A_d = B,
+ * matrix I (x) .. (x) I (x) A_1 + A_d (x) .. (x) A_2 (x) C (Sec. 3).
+ * Modes here are 0-based: A[0] and C act on mode 0, A[1..d-1] on modes 1..
+ * Element-wise:
+ *   Y[i] = sum_j A_1[i_0, j_0] X[j_0, i_1..]
+ *        + sum_j C[i_0, j_0] A_2[i_1, j_1] .. A_d[i_{d-1}, j_{d-1}] X[j].
+ * Evaluated as plain mode products. */
+void FN(oracle_gsylv_apply)(int d, const int64_t* n, const double* const* A, const double* C,
+                            const double* X, double* Y) {
+    int64_t N = 1;
+    for (int mu = 0; mu < d; ++mu) N *= n[mu];
+    double* t0 = (double*)malloc(sizeof(double) * (size_t)N);
+    double* t1 = (double*)malloc(sizeof(double) * (size_t)N);
+    FN(oracle_mode_product)(d, n, 0, A[0], n[0], X, Y);
+    FN(oracle_mode_product)(d, n, 0, C, n[0], X, t0);
+    for (int mu = 1; mu < d; ++mu) {
+        FN(oracle_mode_product)(d, n, mu, A[mu], n[mu], t0, t1);
+        double* sw = t0; t0 = t1; t1 = sw;
+    }
+    for (int64_t o = 0; o < N; ++o) Y[o] += t0[o];
+    free(t0); free(t1);
+}
+
+/* Second-class solve by plain block back-substitution on the assembled
+ * operator (definition of the unique solution, which exists iff the pencil
+ * A_1 + lambda C is regular and none of its eigenvalues is an eigenvalue of
+ * -A_d (x) .. (x) A_2, Sec. 3).  A_mu upper quasi-triangular, C upper
+ * triangular.  The tuples are the products of the 1x1 / 2x2 diagonal blocks
+ * of A_1 .. A_d; tuple p couples to the elements j with j_0 >= start(p_0)
+ * and j_nu >= start(p_nu) for nu >= 1 (A_1 only along mode 0, the product
+ * term over the whole orthant), so tuples are visited by decreasing
+ * hyperplane and each element's right-hand side is
+ *   r_i = B_i - sum over j outside the tuple of (operator entry)(i, j) X[j].
+ * The tuple's unknowns solve the tuple block of the operator by Gaussian
+ * elimination with partial pivoting.  Cost O(N^2): small sizes only. */
+int FN(oracle_gsylv_solve_direct)(int d, const int64_t* n, const double* const* A, const double* C,
+                                  const double* B, double* X) {
+    int64_t stride[ORC_MAXD], N = 1;
+    for (int mu = d - 1; mu >= 0; --mu) { stride[mu] = N; N *= n[mu]; }
+    if (N == 0) return 0;
+    int64_t* bstart[ORC_MAXD];
+    int64_t nb[ORC_MAXD];
+    int rc = 0;
+    for (int mu = 0; mu < d; ++mu) {
+        bstart[mu] = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n[mu] + 1));
+        if (orc_partition(n[mu], A[mu], bstart[mu], &nb[mu]) != 0) rc = ORC_INVALID;
+    }
+    for (int64_t r = 0; r < n[0]; ++r)
+        for (int64_t c = 0; c < r; ++c)
+            if (C[r * n[0] + c] != 0.0) rc = ORC_INVALID;
+    if (rc) { for (int mu = 0; mu < d; ++mu) free(bstart[mu]); return rc; }
+    REAL* Xw = (REAL*)calloc((size_t)N, sizeof(REAL));
+    int64_t smax = 0;
+    for (int mu = 0; mu < d; ++mu) smax += nb[mu] - 1;
+    int64_t lead = 1;
+    for (int mu = 0; mu < d - 1; ++mu) lead *= nb[mu];
+    int failed = 0;
+    /* operator entry between elements i and j (given by coordinates) */
+    #define GSYLV_ENTRY(ii, jj, out)                                              \
+        do {                                                                     \
+            int same = 1;                                                        \
+            for (int nu = 1; nu < d; ++nu) if ((ii)[nu] != (jj)[nu]) same = 0;    \
+            REAL v_ = same ? (REAL)A[0][(ii)[0] * n[0] + (jj)[0]] : 0;           \
+            REAL pr_ = (REAL)C[(ii)[0] * n[0] + (jj)[0]];                        \
+            for (int nu = 1; nu < d && pr_ != 0; ++nu)                           \
+                pr_ *= (REAL)A[nu][(ii)[nu] * n[nu] + (jj)[nu]];                 \
+            (out) = v_ + pr_;                                                    \
+        } while (0)
+    for (int64_t s = smax; s >= 0 && !failed; --s) {
+        #pragma omp parallel for schedule(dynamic, 1) reduction(|: failed)
+        for (int64_t lin = 0; lin < lead; ++lin) {
+            int64_t p[ORC_MAXD];
+            int64_t rem = lin, acc = 0;
+            for (int mu = d - 2; mu >= 0; --mu) { p[mu] = rem % nb[mu]; rem /= nb[mu]; acc += p[mu]; }
+            int64_t last = s - acc;
+            if (last < 0 || last >= nb[d - 1]) continue;
+            p[d - 1] = last;
+            int64_t st[ORC_MAXD], sz[ORC_MAXD];
+            int ne = 1;
+            int64_t region = 1;
+            for (int mu = 0; mu < d; ++mu) {
+                st[mu] = bstart[mu][p[mu]];
+                sz[mu] = bstart[mu][p[mu] + 1] - st[mu];
+                ne *= (int)sz[mu];
+                region *= n[mu] - st[mu];
+            }
+            REAL r[ORC_MAXE], M[ORC_MAXE * ORC_MAXE];
+            int64_t off[ORC_MAXE];
+            for (int e = 0; e < ne; ++e) {
+                int64_t idx[ORC_MAXD];
+                int rr = e;
+                for (int mu = d - 1; mu >= 0; --mu) { idx[mu] = st[mu] + rr % sz[mu]; rr /= (int)sz[mu]; }
+                int64_t o = 0;
+                for (int mu = 0; mu < d; ++mu) o += idx[mu] * stride[mu];
+                off[e] = o;
+                REAL acc2 = (REAL)B[o];
+                for (int64_t t = 0; t < region; ++t) {
+                    int64_t jj[ORC_MAXD];
+                    int64_t rt = t;
+                    int inside = 1;
+                    for (int mu = d - 1; mu >= 0; --mu) {
+                        int64_t ext = n[mu] - st[mu];
+                        jj[mu] = st[mu] + rt % ext; rt /= ext;
+                        if (jj[mu] >= st[mu] + sz[mu]) inside = 0;
+                    }
+                    if (inside) continue;
+                    REAL cpl;
+                    GSYLV_ENTRY(idx, jj, cpl);
+                    if (cpl != 0) {
+                        int64_t oj = 0;
+                        for (int mu = 0; mu < d; ++mu) oj += jj[mu] * stride[mu];
+                        acc2 -= cpl * Xw[oj];
+                    }
+                }
+                r[e] = acc2;
+            }
+            for (int e = 0; e < ne; ++e) {
+                int64_t ie[ORC_MAXD];
+                int re = e;
+                for (int mu = d - 1; mu >= 0; --mu) { ie[mu] = st[mu] + re % sz[mu]; re /= (int)sz[mu]; }
+                for (int f = 0; f < ne; ++f) {
+                    int64_t jf[ORC_MAXD];
+                    int rf = f;
+                    for (int mu = d - 1; mu >= 0; --mu) { jf[mu] = st[mu] + rf % sz[mu]; rf /= (int)sz[mu]; }
+                    REAL m;
+                    GSYLV_ENTRY(ie, jf, m);
+                    M[e * ne + f] = m;
+                }
+            }
+            if (FN(small_gepp)(ne, M, r) != 0) { failed = 1; continue; }
+            for (int e = 0; e < ne; ++e) Xw[off[e]] = r[e];
+        }
+    }
+    #undef GSYLV_ENTRY
+    if (!failed)
+        for (int64_t t = 0; t < N; ++t) X[t] = (double)Xw[t];
+    free(Xw);
+    for (int mu = 0; mu < d; ++mu) free(bstart[mu]);
+    return failed ? ORC_SINGULAR : 0;
+}
+
 /* Gradient of L = <G, X> with respect to T_mu when X solves the Laplace-like
  * equation: with Lam the adjoint solution (sum_nu Lam x_nu T_nu^T = G),
  *   dT_mu[a, b] = - sum over all i with i_mu = a of Lam[i] X[i with i_mu := b],

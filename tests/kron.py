@@ -45,3 +45,13 @@ def vecF(X):
 
 def unvecF(v, shape):
     return v.reshape(shape, order="F")
+
+
+def gsylv_dense(A, C):
+    """Dense matrix of X x_1 A_1 + X x_1 C x_2 A_2 .. x_d A_d on vec_F(X),
+    eq. (1.5): I (x) .. (x) I (x) A_1 + A_d (x) .. (x) A_2 (x) C."""
+    d = len(A)
+    n = [a.shape[0] for a in A]
+    first = kron_all([np.eye(n[nu]) for nu in reversed(range(1, d))] + [A[0]])
+    second = kron_all([A[nu] for nu in reversed(range(1, d))] + [C])
+    return first + second

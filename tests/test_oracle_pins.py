@@ -367,3 +367,96 @@ def test_pair_dense_with_factors_vs_dense(shape):
     Xd = unvecF(np.linalg.solve(pair_dense(p["A"], p["C"]), vecF(p["B"])), p["B"].shape)
     assert rel(X, Xd) < 1e-12
     assert rel(oracle.pair_apply(p["A"], p["C"], X), p["B"]) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Second operator class, eq. (1.5) / (3.1): X x_1 A_1 + X x_1 C x_2 A_2 .. = B
+# ---------------------------------------------------------------------------
+from kron import gsylv_dense  # noqa: E402
+
+
+@pytest.mark.parametrize("shape,bumps", [((7, 6), "every8"), ((5, 4, 6), "aligned"), ((6, 5, 4), "random"),
+                                         ((4, 3, 4, 3), "aligned"), ((9, 9, 2), "every8"),
+                                         ((3, 4, 5, 4), "none")])
+def test_gsylv_solve_vs_dense_kronecker(shape, bumps):
+    p = ti.gsylv_tri(shape, seed=51, bumps=bumps)
+    X = oracle.gsylv_solve(p["A"], p["C"], p["B"])
+    Xd = unvecF(np.linalg.solve(gsylv_dense(p["A"], p["C"]), vecF(p["B"])), p["B"].shape)
+    assert rel(X, Xd) < 1e-12
+    Y = oracle.gsylv_apply(p["A"], p["C"], X)
+    assert rel(unvecF(gsylv_dense(p["A"], p["C"]) @ vecF(X), X.shape), Y) < 1e-14
+    assert rel(Y, p["B"]) < 1e-13
+
+
+def test_gsylv_d2_is_generalized_sylvester():
+    """d = 2: A_1 X + C X A_2^T = B (Sec. 1), i.e. the Sylvester equation
+    (C^{-1} A_1) X + X A_2^T = C^{-1} B, solved by SciPy (Bartels-Stewart)."""
+    p = ti.gsylv_tri((60, 45), seed=52, bumps="every8")
+    X = oracle.gsylv_solve(p["A"], p["C"], p["B"])
+    Ci = np.linalg.inv(p["C"])
+    Xs = sla.solve_sylvester(Ci @ p["A"][0], p["A"][1].T, Ci @ p["B"])
+    assert rel(X, Xs) < 1e-11
+
+
+def test_gsylv_diagonal_closed_form():
+    """Diagonal A_mu, C: X = B / (a_1 + c prod_{mu >= 2} a_mu)."""
+    g = np.random.default_rng(53)
+    shape = (7, 6, 5, 4)
+    a = [1.0 + g.random(n) for n in shape]
+    c = 1.0 + g.random(shape[0])
+    B = g.standard_normal(shape)
+    X = oracle.gsylv_solve([np.diag(v) for v in a], np.diag(c), B)
+    den = a[0][:, None, None, None] + c[:, None, None, None] * (
+        a[1][None, :, None, None] * a[2][None, None, :, None] * a[3][None, None, None, :])
+    assert rel(X, B / den) < 1e-15
+
+
+def test_gsylv_shifted_kronecker_eigenvector_rhs():
+    """Eq. (1.6), A_1 = -lambda I: the operator is A_d (x) .. (x) A_2 (x) C -
+    lambda I.  With B = e_1 o v_2 o v_3 (C e_1 = c_11 e_1 for upper
+    triangular C, A_mu v_mu = alpha_mu v_mu): X = B / (c_11 alpha_2 alpha_3 -
+    lambda).  The same right-hand side with a general A_1 whose first row is
+    a 1x1 block gives B / (a_11 + c_11 alpha_2 alpha_3)."""
+    shape = (12, 17, 13)
+    p = ti.gsylv_tri(shape, seed=54, bumps="every8")
+    alphas, vs = [], []
+    for t, k in zip(p["A"][1:], (9, 3)):
+        assert t[k, k - 1] == 0 and t[k + 1, k] == 0
+        alpha, v = _real_eigvec(t, k)
+        alphas.append(alpha)
+        vs.append(v)
+    e1 = np.zeros(shape[0])
+    e1[0] = 1.0
+    B = np.einsum("i,j,k->ijk", e1, *vs)
+    lam = 0.37
+    Ash = [-lam * np.eye(shape[0])] + p["A"][1:]
+    X = oracle.gsylv_solve(Ash, p["C"], B)
+    assert rel(X, B / (p["C"][0, 0] * alphas[0] * alphas[1] - lam)) < 1e-13
+    assert p["A"][0][1, 0] == 0.0
+    X2 = oracle.gsylv_solve(p["A"], p["C"], B)
+    assert rel(X2, B / (p["A"][0][0, 0] + p["C"][0, 0] * alphas[0] * alphas[1])) < 1e-13
+
+
+def test_gsylv_long_double_agrees():
+    p = ti.gsylv_tri((7, 8, 6), seed=55, bumps="every8")
+    X = oracle.gsylv_solve(p["A"], p["C"], p["B"])
+    Xl = oracle.gsylv_solve(p["A"], p["C"], p["B"], precision="ld")
+    assert rel(X, Xl) < 1e-14
+
+
+def test_gsylv_singular_detected():
+    """A_1 = -C and A_2 = I: the pencil eigenvalue 1 meets -A_2's eigenvalue."""
+    n = 4
+    C = np.triu(np.ones((n, n)))
+    with pytest.raises(oracle.OracleError):
+        oracle.gsylv_solve([-C, np.eye(3), np.eye(2)], C, np.ones((n, 3, 2)))
+
+
+@pytest.mark.parametrize("shape", [(6, 5, 4), (4, 3, 4, 3), (8, 7)])
+def test_gsylv_dense_with_factors_vs_dense(shape):
+    """Algorithm 4 with known factors against the assembled dense operator."""
+    p = ti.gsylv_dense(shape, seed=56, bumps="random")
+    X = oracle.gsylv_dense_solve_with_factors(p["Q"], p["S"], p["T"], p["Z"], p["U"], p["Tq"], p["B"])
+    Xd = unvecF(np.linalg.solve(gsylv_dense(p["A"], p["C"]), vecF(p["B"])), p["B"].shape)
+    assert rel(X, Xd) < 1e-12
+    assert rel(oracle.gsylv_apply(p["A"], p["C"], X), p["B"]) < 1e-13

@@ -150,6 +150,32 @@ def pair_tri(shape, seed=0, bumps="every8"):
     return {"A": A, "C": C, "B": B}
 
 
+def gsylv_tri(shape, seed=0, bumps="every8"):
+    """Second operator class (eq. (3.1)) with triangular coefficients:
+    X x_1 A_1 + X x_1 C x_2 A_2 .. x_d A_d = B, A_mu upper quasi-triangular
+    as laplace_tri, C upper triangular with diagonal U[1,2]."""
+    shape = tuple(int(x) for x in shape)
+    A = [quasi_triangular(n, rng(seed, ROLE_T, mu), bumps) for mu, n in enumerate(shape)]
+    C = upper_triangular(shape[0], rng(seed, ROLE_C, 0))
+    B = gaussian_tensor(shape, rng(seed, ROLE_B))
+    return {"A": A, "C": C, "B": B}
+
+
+def gsylv_dense(shape, seed=0, bumps="every8"):
+    """Dense second class (Algorithm 4): A_1 = Q S Z^T, C = Q T Z^T with
+    (S, T) the triangular pair of gsylv_tri and A_mu = U_mu Tq_mu U_mu^T
+    (mu >= 2), all orthogonal factors random (so the reductions are known)."""
+    p = gsylv_tri(shape, seed, bumps)
+    Q = random_orthogonal(shape[0], rng(seed, ROLE_Q, 0))
+    Z = random_orthogonal(shape[0], rng(seed, ROLE_Z, 0))
+    U = [random_orthogonal(n, rng(seed, ROLE_Q, mu)) for mu, n in enumerate(shape) if mu >= 1]
+    A = [np.ascontiguousarray(Q @ p["A"][0] @ Z.T)]
+    A += [np.ascontiguousarray(u @ t @ u.T) for u, t in zip(U, p["A"][1:])]
+    Cd = np.ascontiguousarray(Q @ p["C"] @ Z.T)
+    return {"A": A, "C": Cd, "B": p["B"], "S": p["A"][0], "T": p["C"], "Q": Q, "Z": Z, "U": U,
+            "Tq": p["A"][1:]}
+
+
 def pair_dense(shape, seed=0, bumps="every8"):
     """Dense pair form: A_mu = Q_mu S_mu Z_mu^T, C_mu = Q_mu T_mu Z_mu^T with
     (S_mu, T_mu) the triangular pair of pair_tri and Q_mu, Z_mu random
