@@ -84,11 +84,12 @@ typedef struct {
 } tt_opts;
 
 /* Upper bound of the device workspace (bytes) that one single-problem call
- * of solve_tri_tensor (Laplace-like or pair form), solve_general_tensor or
- * solve_backward with order d, mode sizes n[0..d-1], precision prec
- * (tt_prec) and the default leaf size (opts->nmin = 0) needs, whatever the
- * coefficients' 2x2-block pattern.  Host-only; 0 on invalid arguments.
- * Batched calls need the sum over their problems. */
+ * of solve_tri_tensor (Laplace-like or pair form), solve_general_tensor,
+ * solve_backward, solve_gsylv_tensor or solve_gsylv_general_tensor with order
+ * d, mode sizes n[0..d-1], precision prec (tt_prec) and the default leaf
+ * size (opts->nmin = 0) needs, whatever the coefficients' 2x2-block pattern.
+ * Host-only; 0 on invalid arguments.  Batched calls need the sum over their
+ * problems. */
 size_t tt_workspace_bytes(int d, const int64_t* n, int prec);
 
 /* Fill *o with defaults (nmin 0, TT_FP64, tol 1e-13, max_iter 10, stream and
@@ -188,6 +189,40 @@ int solve_backward(int d, const int64_t* n, const double* const* T,
                    const double* X, const double* G, double* dB,
                    double* const* dT, int dense_grad, tt_opts* opts);
 
+/* ---------------------------------------------------------------------------
+ * The second operator class of the paper, eq. (1.5) / (3.1) (generalized
+ * Sylvester equations with Kronecker structure, Sec. 3):
+ *     X x_1 A_1 + X x_1 C x_2 A_2 x_3 ... x_d A_d = B,
+ * matrix I (x) .. (x) I (x) A_1 + A_d (x) .. (x) A_2 (x) C.  The solution is
+ * unique iff the pencil A_1 + lambda C is regular and none of its
+ * eigenvalues is an eigenvalue of -A_d (x) .. (x) A_2 (Sec. 3).  With
+ * A_1 = -lambda I this is the shifted Kronecker product of eq. (1.6).
+ *
+ * solve_gsylv_tensor: triangular coefficients (the output of Algorithm 4's
+ *   reductions): A[mu] DEVICE pointers to upper quasi-triangular n[mu] x n[mu]
+ *   matrices (row-major), C a DEVICE pointer to an upper triangular n[0] x
+ *   n[0] matrix with nonzero diagonal.  The equation is reduced exactly by
+ *   C^{-1} along mode 1: X x_1 (C^{-1} A_1) + X x_2 A_2 .. x_d A_d =
+ *   B x_1 C^{-1} (C^{-1} A_1 keeps the pattern of A_1); orders 1 and 2 are
+ *   then Laplace-like, orders 3 and 4 run the recursion of Algorithm 5 as
+ *   the hyperplane schedule of solve_tri_tensor with the second-class
+ *   updates (up to d products, telescoped through partial products) and
+ *   leaves.  d = 1 .. 4.
+ * solve_gsylv_general_tensor: dense coefficients, Algorithm 4: host QZ of
+ *   (A_1, C), host real Schur of A_2 .. A_d, the transforms on the GPU.
+ *   A_host[mu], C_host: HOST row-major matrices.
+ * B, X: device tensors as for solve_tri_tensor; X may alias B.  FP64 only
+ * (opts->prec must be TT_FP64).  opts->nmin = 0 takes 8 (d = 3) / 4 (d = 4).
+ * Errors: TT_EINVAL (arguments, structure, C not upper triangular or with a
+ * zero diagonal entry, no QZ / QR convergence), TT_ESINGULAR (zero pivot or
+ * non-finite value: the uniqueness condition fails), TT_ENOMEM, TT_EHIP.
+ * ------------------------------------------------------------------------- */
+int solve_gsylv_tensor(int d, const int64_t* n, const double* const* A, const double* C,
+                       const double* B, double* X, tt_opts* opts);
+int solve_gsylv_general_tensor(int d, const int64_t* n, const double* const* A_host,
+                               const double* C_host, const double* B, double* X,
+                               tt_opts* opts);
+
 /* Batched forms: count independent problems of possibly different shapes,
  * solved together (one launch sequence for the whole batch).  d[b], n[b],
  * T[b], B[b], X[b] describe problem b exactly as in solve_tri_tensor
@@ -243,6 +278,15 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n,
  * precision), TT_ENOMEM. */
 int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
                                 const double* const* C_host, const tt_opts* opts);
+
+/* Plans of the second class (see solve_gsylv_tensor): triangular
+ * coefficients on the device (tt_plan_create_gsylv) or dense coefficients on
+ * the host (tt_plan_create_gsylv_general, Algorithm 4).  Solve with
+ * tt_plan_solve / tt_plan_solve_graph. */
+int tt_plan_create_gsylv(tt_plan* out, int d, const int64_t* n, const double* const* A,
+                         const double* C, const tt_opts* opts);
+int tt_plan_create_gsylv_general(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
+                                 const double* C_host, const tt_opts* opts);
 
 /* Coefficient gradients with a reusable plan (the adjoint's second half):
  * for every problem i of a triangular plan (tt_plan_create /

@@ -47,6 +47,7 @@ SYMBOLS = [
     "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
     "tt_copy_device", "tt_workspace_bytes", "solve_tri_tensor_noalloc",
+    "solve_gsylv_tensor", "solve_gsylv_general_tensor", "tt_plan_create_gsylv", "tt_plan_create_gsylv_general",
 ]
 
 
@@ -65,6 +66,11 @@ def lib():
         L.tt_workspace_bytes.restype = ctypes.c_size_t
         L.solve_tri_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_tri_tensor_noalloc.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_gsylv_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.solve_gsylv_general_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, ctypes.POINTER(Opts)]
+        L.tt_plan_create_gsylv.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp, ctypes.POINTER(Opts)]
+        L.tt_plan_create_gsylv_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp,
+                                                   ctypes.POINTER(Opts)]
         L.solve_general_tensor.argtypes = [ctypes.c_int, i64p, vp, vp, vp, ctypes.POINTER(Opts)]
         L.solve_backward.argtypes = [ctypes.c_int, i64p, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts)]
         L.solve_tri_tensor_batched.argtypes = [ctypes.c_int, ip, vp, vp, vp, vp, ctypes.POINTER(Opts)]
@@ -179,6 +185,34 @@ def solve_tri_noalloc(T, B, X, C=None, nmin=0, stream=None):
     return X
 
 
+def solve_gsylv(A, C, B, X=None, nmin=0, stream=None, workspace=None):
+    """Second operator class (eq. (3.1)): X x_1 A_1 + X x_1 C x_2 A_2 .. x_d
+    A_d = B with upper quasi-triangular A_mu and upper triangular C, all
+    float64 CUDA tensors (C acts on the first mode)."""
+    import torch
+    if X is None:
+        X = torch.empty_like(B)
+    ap = _ptr_array([_dev(a) for a in A])
+    o = _opts(nmin=nmin, stream=stream, workspace=workspace)
+    _check(lib().solve_gsylv_tensor(B.dim(), _shape(B.shape), ap, ctypes.c_void_p(_dev(C)), _dev(B), _dev(X),
+                                    ctypes.byref(o)))
+    return X
+
+
+def solve_gsylv_general(A, C, B, X=None, nmin=0, stream=None, workspace=None):
+    """Second operator class with dense HOST coefficients (Algorithm 4: host
+    QZ of (A_1, C) and real Schur of A_2 .. A_d, GPU transforms and solve)."""
+    import torch
+    if X is None:
+        X = torch.empty_like(B)
+    mats, ap = _host_mats(A)
+    Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    o = _opts(nmin=nmin, stream=stream, workspace=workspace)
+    _check(lib().solve_gsylv_general_tensor(B.dim(), _shape(B.shape), ap, ctypes.c_void_p(Cm.ctypes.data), _dev(B),
+                                            _dev(X), ctypes.byref(o)))
+    return X
+
+
 def _host_mats(A):
     mats = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in A]
     return mats, _ptr_array([m.ctypes.data for m in mats])
@@ -267,10 +301,24 @@ class Plan:
     (Algorithm 1 pipeline; with C: host QZ, Sec. 3)."""
 
     def __init__(self, T, shape=None, nmin=0, trans=False, batch_T=None, batch_shapes=None, C=None,
-                 general=False, prec=TT_FP64, tol=1e-13, max_iter=10):
+                 general=False, prec=TT_FP64, tol=1e-13, max_iter=10, gsylv=False):
         self._h = ctypes.c_void_p()
         o = _opts(nmin=nmin, prec=prec, tol=tol, max_iter=max_iter)
-        if general and C is not None:
+        if gsylv:
+            # second operator class (eq. (3.1)): T = A_1 .. A_d, C acts on mode 1
+            self.count = 1
+            self.shapes = [tuple(int(x) for x in shape)]
+            if general:
+                mats, ap = _host_mats(T)
+                Cm = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+                self._keep = [mats, ap, Cm]
+                _check(lib().tt_plan_create_gsylv_general(ctypes.byref(self._h), len(shape), _shape(shape), ap,
+                                                          ctypes.c_void_p(Cm.ctypes.data), ctypes.byref(o)))
+            else:
+                self._keep = [_ptr_array([_dev(t) for t in T])]
+                _check(lib().tt_plan_create_gsylv(ctypes.byref(self._h), len(shape), _shape(shape), self._keep[0],
+                                                  ctypes.c_void_p(_dev(C)), ctypes.byref(o)))
+        elif general and C is not None:
             mats, ap = _host_mats(T)
             cmats, cp = _host_mats(C)
             self._keep = [mats, ap, cmats, cp]

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libtt.so")
-SOURCES = ["tt_api.hip", "tt_kernels.hip", "tt_leaf.hip", "tt_plan.cpp", "tt_schur.cpp", "tt_dense.hip"]
+SOURCES = ["tt_api.hip", "tt_kernels.hip", "tt_leaf.hip", "tt_leaf2.hip", "tt_plan.cpp", "tt_schur.cpp", "tt_dense.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

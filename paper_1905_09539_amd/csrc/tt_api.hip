@@ -36,8 +36,11 @@ struct PtrPack {
 __global__ void set_x_ptrs_kernel(ProbDesc* probs, PtrPack pack, int first, int count) {
     int i = threadIdx.x;
     if (i < count) {
-        probs[first + i].X = pack.p[i];
-        probs[first + i].B = pack.b[i];
+        ProbDesc& P = probs[first + i];
+        P.X = pack.p[i];
+        P.B = pack.b[i];
+        // update sources: X, or the second class's partial products
+        for (int mu = 0; mu < kMaxD; ++mu) P.S[mu] = (P.cls == 1 && mu >= 2) ? P.W[mu - 1] : pack.p[i];
     }
 }
 
@@ -341,6 +344,15 @@ int finish_plan(tt_plan_s* P, int nmin) {
     char* da = nullptr;
     if ((rc = dev_alloc(P, cbytes, (void**)&dc, "coefficients"))) return rc;
     if (abytes > 0 && (rc = dev_alloc(P, abytes, (void**)&da, "update accumulators"))) return rc;
+    // second class: the partial products W_1 .. W_{D-2} written by the leaves
+    std::vector<std::vector<double*>> wt(s.probs.size());
+    if (s.cls == 1)
+        for (size_t i = 0; i < s.probs.size(); ++i)
+            for (int k = 1; k <= s.D - 2; ++k) {
+                double* w = nullptr;
+                if ((rc = alloc_tensor(P, s.probs[i].N, &w))) return rc;
+                wt[i].push_back(w);
+            }
     std::vector<char> image(cbytes, 0);
     std::vector<ProbDesc> pd(s.probs.size());
     size_t co = 0, ao = 0;
@@ -352,6 +364,8 @@ int finish_plan(tt_plan_s* P, int nmin) {
             d.n[mu] = (mu < s.D) ? hp.n[mu] : 1;
             d.stride[mu] = (mu < s.D) ? hp.stride[mu] : 0;
         }
+        d.cls = s.cls;
+        for (size_t k = 0; k < wt[i].size(); ++k) d.W[k + 1] = wt[i][k];
         for (int mu = 0; mu < s.D; ++mu) {
             if (!hp.T[mu].empty()) std::memcpy(image.data() + co, hp.T[mu].data(), sizeof(double) * hp.T[mu].size());
             d.T[mu] = (double*)(dc + co);
@@ -416,13 +430,21 @@ struct ProfEvents {
     bool serial = false;  // every launch on the caller's stream
 };
 
+// The leaf launch of a schedule's operator class.
+hipError_t launch_leaf_any(const Schedule& s, const LeafDesc* leaves, int64_t first, int64_t count,
+                           const ProbDesc* probs, const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs,
+                           int* status, const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st) {
+    if (s.cls == 1) return launch_leaf2(s.D, leaves, first, count, probs, shapes, ents, hoffs, status, bmax, st);
+    return launch_leaf(s.D, leaves, first, count, probs, shapes, ents, hoffs, status, bmax, maxtup, maxcpl, maxH, st);
+}
+
 int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int lp = 0) {
     Schedule& s = P->sched;
     if (P->serial_only) {
         // one stream: wave k's leaves, then the updates ready after them
         const int leaf_lds = leaf_lds_bytes(s.D, s.bmax, s.maxtup, s.maxcpl, s.maxH);
         for (const Wave& wv : s.waves) {
-            TT_HIP_CHECK(launch_leaf(s.D, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
+            TT_HIP_CHECK(launch_leaf_any(s, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
                                      P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH,
                                      st));
             TT_HIP_CHECK(launch_update(s.D, P->d_tasks, P->d_items, wv.item_first, wv.item_count, P->d_probs, lp,
@@ -439,7 +461,7 @@ int run_schedule(tt_plan_s* P, hipStream_t st, ProfEvents* prof = nullptr, int l
         const Wave& wv = s.waves[k];
         if (k >= 1) TT_HIP_CHECK(hipStreamWaitEvent(st, P->evU[k - 1], 0));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->lb[k], st));
-        TT_HIP_CHECK(launch_leaf(s.D, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
+        TT_HIP_CHECK(launch_leaf_any(s, P->d_leaves, wv.leaf_first, wv.leaf_count, P->d_probs, P->d_shapes,
                                  P->d_ents, P->d_hoffs, P->d_status, s.bmax, s.maxtup, s.maxcpl, s.maxH, st));
         if (prof) TT_HIP_CHECK(hipEventRecord(prof->la[k], st));
         TT_HIP_CHECK(hipEventRecord(P->evL[k], st));
@@ -514,7 +536,11 @@ void mode_view(const HostProblem& hp, int mu, int64_t& L, int64_t& nm, int64_t& 
 int apply_chain(tt_plan_s* P, const double* src, double* fin, double* other, const std::vector<double*>& mats,
                 int lp, hipStream_t st) {
     const HostProblem& hp = P->sched.probs[0];
-    const int m = (int)mats.size();
+    // the modes that carry a matrix (a NULL entry leaves its mode unchanged)
+    std::vector<int> modes;
+    for (size_t i = 0; i < mats.size(); ++i)
+        if (mats[i]) modes.push_back((int)i);
+    const int m = (int)modes.size();
     if (m == 0) {
         if (src != fin) TT_HIP_CHECK(launch_copy(src, fin, hp.N, st));
         return TT_OK;
@@ -529,8 +555,9 @@ int apply_chain(tt_plan_s* P, const double* src, double* fin, double* other, con
     for (int i = 0; i < m; ++i) {
         double* tgt = ((m - 1 - i) % 2 == 0) ? fin : other;
         int64_t L, nm, R;
-        mode_view(hp, i, L, nm, R);
-        TT_HIP_CHECK(launch_modeprod(cur, tgt, nullptr, mats[(size_t)i], L, (int)nm, (int)nm, R, 1.0, 0.0, lp, st));
+        mode_view(hp, modes[(size_t)i], L, nm, R);
+        TT_HIP_CHECK(launch_modeprod(cur, tgt, nullptr, mats[(size_t)modes[(size_t)i]], L, (int)nm, (int)nm, R, 1.0,
+                                     0.0, lp, st));
         cur = tgt;
     }
     return TT_OK;
@@ -664,38 +691,26 @@ int plan_begin(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::vec
 //                       where per pencil and mode the targets of one tree
 //                       level cover at most n rows, for both task types;
 //   tuple shapes     distinct tuple counts per mode <= min(m, leaf edge).
-size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
-    if (d < 1 || d > 4 || !n) return 0;
-    const int D = (d == 4) ? 4 : 3;
-    const int b = (D >= 4) ? 8 : 16;  // default leaf edge (build_schedule)
-    int64_t nn[kMaxD] = {1, 1, 1, 1};
-    for (int mu = 0; mu < d; ++mu) {
-        if (n[mu] < 0) return 0;
-        nn[D - d + mu] = n[mu];
-    }
+// Tables, coefficient copies, block starts, accumulators and status word of
+// a plan with leaf edge b (see plan_bound_bytes).
+static double plan_tables_bound(int D, const int64_t* nn, int b, double N) {
     auto al = align256;
-    double N = 1;
-    for (int mu = 0; mu < D; ++mu) N *= (double)nn[mu];
-    size_t coef = 0, mats = 0;
-    double L = 1, S = 1, ents = 1, tiles_idx = 0, W = 1, lev_rows = 0, nmax = 1;
+    size_t coef = 0;
+    double L = 1, S = 1, ents = 1, W = 1, lev_rows = 0;
     int64_t m[kMaxD], bm[kMaxD];
     for (int mu = 0; mu < D; ++mu) {
         const int64_t nm = nn[mu];
         m[mu] = (nm == 0) ? 0 : std::min<int64_t>(nm, (nm + b - 1) / b + 1);
         bm[mu] = std::max<int64_t>(1, std::min<int64_t>(nm, b + 1));
         coef += al(sizeof(double) * (size_t)std::max<int64_t>(1, nm * nm)) + al(sizeof(int32_t) * (size_t)(m[mu] + 1));
-        mats += al(sizeof(double) * (size_t)std::max<int64_t>(1, nm * nm));
         L *= (double)m[mu];
         W += (double)std::max<int64_t>(0, m[mu] - 1);
-        nmax = std::max(nmax, (double)nm);
         const int64_t distinct = std::min<int64_t>(m[mu], bm[mu]);
         S *= (double)std::max<int64_t>(1, distinct);
         double tsum = 0;  // sum of the largest `distinct` tuple counts <= bm
         for (int64_t k = 0; k < distinct; ++k) tsum += (double)(bm[mu] - k);
         ents *= std::max(1.0, tsum);
     }
-    if (N == 0) return 4096;
-    (void)tiles_idx;
     double Pmax = 1;
     for (int mu = 0; mu < D - 1; ++mu) Pmax *= (double)bm[mu];
     const double tasks = 2.0 * D * L;
@@ -710,9 +725,29 @@ size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
                    ents * sizeof(uint16_t) + S * (Hmax + 1) * sizeof(int32_t) + tasks * sizeof(UpdDesc) +
                    items * sizeof(WorkItem) + 9 * 256.0;  // alignment of the tables, status word
     bytes += (double)(D - 1) * (double)al((size_t)(8.0 * N));  // update accumulators
-    // the largest of the extras: dense pipeline (pre, post, one tensor)
-    // with refinement (dense A, residual tensor, norm partial sums), the
-    // pair form (pre, one tensor), the adjoint's gradient workspace
+    return bytes;
+}
+
+size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
+    if (d < 1 || d > 4 || !n) return 0;
+    const int D = (d == 4) ? 4 : 3;
+    int64_t nn[kMaxD] = {1, 1, 1, 1};
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] < 0) return 0;
+        nn[D - d + mu] = n[mu];
+    }
+    auto al = align256;
+    double N = 1;
+    size_t mats = 0;
+    for (int mu = 0; mu < D; ++mu) {
+        N *= (double)nn[mu];
+        mats += al(sizeof(double) * (size_t)std::max<int64_t>(1, nn[mu] * nn[mu]));
+    }
+    if (N == 0) return 4096;
+    // Laplace-like, pair, dense and adjoint calls: default leaf edge 16 / 8,
+    // plus the largest of their extras: dense pipeline (pre, post, one
+    // tensor) with refinement (dense A, residual tensor, norm partial sums),
+    // the pair form (pre, one tensor), the adjoint's gradient workspace
     const double tensor = (double)al((size_t)(8.0 * N));
     double general = 2.0 * (double)mats + tensor;
     if (prec != TT_FP64) general += (double)mats + tensor + al(sizeof(double) * 2 * (size_t)sumsq_blocks());
@@ -728,9 +763,12 @@ size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
         grads += ns * (double)nn[mu] * (double)nn[mu] * 8.0;
     }
     grads = (double)al((size_t)grads);
-    bytes += std::max(std::max(general, pair), grads);
-    (void)nmax;
-    return (size_t)std::ceil(bytes) + 4096;
+    const double lap = plan_tables_bound(D, nn, (D >= 4) ? 8 : 16, N) + std::max(std::max(general, pair), grads);
+    // second class: leaf edge 8 / 4, partial products W_1 .. W_{D-2}, pre
+    // and post matrices and one pipeline tensor
+    const double cls2 = plan_tables_bound(D, nn, (D >= 4) ? 4 : 8, N) + (double)(D - 2) * tensor + 2.0 * (double)mats +
+                        tensor;
+    return (size_t)std::ceil(std::max(lap, cls2)) + 4096;
 }
 
 // Scratch of the allocation-free solve (solve_tri_tensor_noalloc): the
@@ -1077,6 +1115,173 @@ int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const dou
     P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P.release();
     return TT_OK;
+}
+
+// Second operator class (Sec. 3, eq. (3.1)) with triangular coefficients,
+// after the exact reduction by C^{-1} along mode 1 (C upper triangular, so
+// C^{-1} A_1 keeps the quasi-triangular pattern of A_1, and mode products in
+// different modes commute):
+//   X x_1 (C^{-1} A_1) + X x_2 A_2 .. x_d A_d = B x_1 C^{-1}.
+// Orders 1 and 2 are Laplace-like after the reduction (d = 1: the empty
+// product is the identity, (C^{-1} A_1 + I) x = C^{-1} b; d = 2: a
+// Sylvester equation); orders 3 and 4 use the second-class leaves.
+// A[mu], pre[mu]: host row-major; pre: mode products applied to B first
+// (empty vectors skip a mode); post likewise after the solve.
+static int gsylv_plan(tt_plan_s* P, int d, const int64_t* n, std::vector<std::vector<double>> T,
+                      const std::vector<std::vector<double>>& pre, const std::vector<std::vector<double>>& post,
+                      const tt_opts* opts) {
+    int rc;
+    if (d == 1) {
+        const int64_t m = n[0];
+        for (int64_t i = 0; i < m; ++i) T[0][(size_t)(i * m + i)] += 1.0;
+    }
+    if ((rc = plan_begin(P, d, n, T, 0))) return rc;
+    P->sched.cls = (d >= 3) ? 1 : 0;
+    P->kind = post.empty() ? KIND_PAIR : KIND_GENERAL;
+    if ((rc = finish_plan(P, opts ? opts->nmin : 0))) return rc;
+    const HostProblem& hp = P->sched.probs[0];
+    P->pre.assign((size_t)d, nullptr);
+    for (int mu = 0; mu < d; ++mu)
+        if (!pre[(size_t)mu].empty() && (rc = upload_matrix(P, pre[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
+    if (!post.empty()) {
+        P->post.assign((size_t)d, nullptr);
+        for (int mu = 0; mu < d; ++mu)
+            if (!post[(size_t)mu].empty() && (rc = upload_matrix(P, post[(size_t)mu], &P->post[(size_t)mu])))
+                return rc;
+    }
+    if ((rc = alloc_tensor(P, hp.N, &P->W))) return rc;
+    int products = 0;
+    for (const auto& m : pre) products += m.empty() ? 0 : 1;
+    for (const auto& m : post) products += m.empty() ? 0 : 1;
+    double f = 0;
+    const int lead = hp.D - hp.d_user;
+    for (int mu = 0; mu < hp.d_user; ++mu)
+        if (!pre[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
+    for (int mu = 0; mu < (int)post.size(); ++mu)
+        if (!post[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
+    P->pipe_flops = P->sched.stats.flops + f;
+    return TT_OK;
+}
+
+int tt_plan_create_gsylv(tt_plan* out, int d, const int64_t* n, const double* const* A, const double* C,
+                         const tt_opts* opts) {
+    if (!out) return fail(TT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A || !C) return fail(TT_EINVAL, "coefficient array is NULL");
+    if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "the second operator class is FP64 only");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
+    HostProblem probe;
+    int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
+    if (rc) return rc;
+    std::vector<std::vector<double>> T, Cm, Cinv;
+    if ((rc = fetch_matrices(d, n, A, T))) return rc;
+    const double* Cp[1] = {C};
+    if ((rc = fetch_matrices(1, n, Cp, Cm))) return rc;
+    std::vector<std::vector<double>> T0(1, T[0]);
+    if ((rc = pair_reduce(1, n, T0, Cm, Cinv))) return rc;  // T0 <- C^{-1} A_1
+    T[0] = T0[0];
+    std::vector<std::vector<double>> pre((size_t)d);
+    pre[0] = Cinv[0];
+    if ((rc = gsylv_plan(P.get(), d, n, T, pre, {}, opts))) return rc;
+    P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P.release();
+    return TT_OK;
+}
+
+// Algorithm 4: real generalized Schur decomposition A_1 = Q S Z^T,
+// C = Q T Z^T (host QZ) and real Schur decompositions A_mu = U_mu Tq_mu
+// U_mu^T (mu >= 2, host); then B~ = B x_1 (T^{-1} Q^T) x_mu U_mu^T, the
+// triangular second-class solve with T^{-1} S and Tq_mu, and
+// X = X~ x_1 Z x_mu U_mu.
+int tt_plan_create_gsylv_general(tt_plan* out, int d, const int64_t* n, const double* const* A_host,
+                                 const double* C_host, const tt_opts* opts) {
+    if (!out) return fail(TT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!A_host || !C_host) return fail(TT_EINVAL, "coefficient array is NULL");
+    if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "the second operator class is FP64 only");
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+    adopt_workspace(P.get(), opts);
+    HostProblem probe;
+    int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
+    if (rc) return rc;
+    for (int mu = 0; mu < d; ++mu) {
+        if (n[mu] > 16384) return fail(TT_EINVAL, "mode size too large for the host Schur decomposition");
+        if (!A_host[mu] && n[mu] > 0) return fail(TT_EINVAL, "coefficient pointer is NULL");
+    }
+    const int64_t n0 = n[0];
+    const size_t nn0 = (size_t)(n0 * n0);
+    std::vector<std::vector<double>> T((size_t)d), pre((size_t)d), post((size_t)d);
+    std::vector<double> S(nn0), Tc(nn0), Q(nn0), Z(nn0);
+    std::vector<std::vector<double>> U((size_t)d);
+    std::vector<int> rcs((size_t)d, TT_OK);
+    std::vector<std::string> msg((size_t)d);
+    {
+        std::vector<std::thread> th;
+        th.emplace_back([&] {
+            rcs[0] = qz_real((int)n0, A_host[0], C_host, S.data(), Tc.data(), Q.data(), Z.data(), msg[0]);
+        });
+        for (int mu = 1; mu < d; ++mu)
+            th.emplace_back([&, mu] {
+                const size_t nn = (size_t)(n[mu] * n[mu]);
+                T[(size_t)mu].assign(nn, 0.0);
+                U[(size_t)mu].assign(nn, 0.0);
+                rcs[(size_t)mu] = schur_real((int)n[mu], A_host[mu], T[(size_t)mu].data(), U[(size_t)mu].data(),
+                                             msg[(size_t)mu]);
+            });
+        for (auto& t : th) t.join();
+        for (int mu = 0; mu < d; ++mu)
+            if (rcs[(size_t)mu]) return fail(rcs[(size_t)mu], "mode " + std::to_string(mu) + ": " + msg[(size_t)mu]);
+    }
+    P->schur_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    std::vector<std::vector<double>> S1(1, S), T1(1, Tc), Tinv;
+    if ((rc = pair_reduce(1, n, S1, T1, Tinv))) return rc;  // S <- T^{-1} S
+    T[0] = S1[0];
+    // pre: mode 1 T^{-1} Q^T, modes mu >= 2 U_mu^T; post: Z, U_mu
+    pre[0].assign(nn0, 0.0);
+    for (int64_t i = 0; i < n0; ++i)
+        for (int64_t k = i; k < n0; ++k) {
+            const double f = Tinv[0][(size_t)(i * n0 + k)];
+            if (f == 0.0) continue;
+            for (int64_t j = 0; j < n0; ++j) pre[0][(size_t)(i * n0 + j)] += f * Q[(size_t)(j * n0 + k)];
+        }
+    post[0] = Z;
+    for (int mu = 1; mu < d; ++mu) {
+        const int64_t m = n[mu];
+        pre[(size_t)mu].assign((size_t)(m * m), 0.0);
+        for (int64_t i = 0; i < m; ++i)
+            for (int64_t j = 0; j < m; ++j) pre[(size_t)mu][(size_t)(i * m + j)] = U[(size_t)mu][(size_t)(j * m + i)];
+        post[(size_t)mu] = U[(size_t)mu];
+    }
+    if ((rc = gsylv_plan(P.get(), d, n, T, pre, post, opts))) return rc;
+    P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = P.release();
+    return TT_OK;
+}
+
+int solve_gsylv_tensor(int d, const int64_t* n, const double* const* A, const double* C, const double* B,
+                       double* X, tt_opts* opts) {
+    tt_plan p = nullptr;
+    int rc = tt_plan_create_gsylv(&p, d, n, A, C, opts);
+    if (rc) return rc;
+    std::unique_ptr<tt_plan_s> guard(p);
+    rc = tt_plan_solve(p, B, X, opts ? (hipStream_t)opts->stream : nullptr);
+    if (rc) return rc;
+    return tt_plan_status(p);
+}
+
+int solve_gsylv_general_tensor(int d, const int64_t* n, const double* const* A_host, const double* C_host,
+                               const double* B, double* X, tt_opts* opts) {
+    tt_plan p = nullptr;
+    int rc = tt_plan_create_gsylv_general(&p, d, n, A_host, C_host, opts);
+    if (rc) return rc;
+    std::unique_ptr<tt_plan_s> guard(p);
+    rc = tt_plan_solve(p, B, X, opts ? (hipStream_t)opts->stream : nullptr);
+    if (opts) opts->info[2] = p->build_seconds;
+    if (rc) return rc;
+    return tt_plan_status(p);
 }
 
 int tt_plan_solve_batched(tt_plan plan, const double* const* B, double* const* X, void* stream) {

@@ -41,6 +41,18 @@ struct ProbDesc {
     const int32_t* bst[kMaxD];   // block starts per mode (device), m+1 entries
     int64_t n[kMaxD];
     int64_t stride[kMaxD];
+    // Second operator class (Sec. 3, after the exact C^{-1} reduction):
+    //   X x_0 T_0 + X x_1 A_1 x_2 A_2 .. x_{D-1} A_{D-1} = B.
+    // Mode-mu updates read S[mu]: X for mode 0 and 1, the partial products
+    // W[mu-1] for mu >= 2, where W[k] (k = 1 .. D-2), written by each leaf,
+    // holds sum over j_1 >= i_1 .. j_k >= i_k of A_1[i_1, j_1] .. A_k[i_k, j_k]
+    // X[i_0, j_1 .. j_k, i_{k+1} ..] (block-wise: the leaf's diagonal blocks
+    // applied to its solution plus the accumulator of that mode).  The
+    // Laplace-like form reads X in every mode.
+    const double* S[kMaxD];
+    double* W[kMaxD];
+    int32_t cls;                 // 0: Laplace-like, 1: second class
+    int32_t pad_;
 };
 
 // One leaf block: problem index and block coordinates.
@@ -141,6 +153,7 @@ struct PlanStats {
 // Host-side schedule (built without touching the GPU).
 struct Schedule {
     int D = 3;
+    int cls = 0;                 // 0: Laplace-like, 1: second class (Sec. 3)
     std::vector<HostProblem> probs;
     std::vector<LeafDesc> leaves;
     std::vector<UpdDesc> tasks;
@@ -164,6 +177,11 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
 hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
                        const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
                        const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st);
+// Leaves of the second operator class (tt_leaf2.hip), one wave per block.
+hipError_t launch_leaf2(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
+                        const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
+                        const int* bmax, hipStream_t st);
+int leaf2_lds_bytes(int D, const int* bmax);
 // leaf_lds: LDS bytes of a leaf workgroup that should fit on a CU beside two
 // update workgroups (0: no limit on update workgroups per CU)
 hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int64_t first,

@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
     const UpdDesc t = tasks[wi.task];
     const ProbDesc& P = probs[t.prob];
     const int mode = t.mode;
-    const gdouble* __restrict__ X = to_global(P.X);
+    // source of the products: X, or a partial product of the second class
+    const gdouble* __restrict__ X = to_global(P.S[mode]);
     gdouble* __restrict__ C = to_global((mode == 0) ? P.X : P.A[mode]);
     const gdouble* __restrict__ T = to_global(P.T[mode]);
     const int64_t nmu = P.n[mode];

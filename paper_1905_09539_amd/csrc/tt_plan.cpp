@@ -163,7 +163,9 @@ static int32_t shape_index(Schedule& s, std::map<std::array<int, kMaxD>, int32_t
 
 int build_schedule(Schedule& s, int nmin, std::string& err) {
     const int D = s.D;
-    if (nmin <= 0) nmin = (D >= 4) ? 8 : 16;
+    // default leaf edge: 16 (order 3) / 8 (order 4); the second class's
+    // leaves (one wave, products over the orthant) take 8 / 4
+    if (nmin <= 0) nmin = (s.cls == 1) ? ((D >= 4) ? 4 : 8) : ((D >= 4) ? 8 : 16);
     if (nmin < 2) nmin = 2;
     if (nmin > 20) {
         err = "nmin must be at most 20";
@@ -481,7 +483,8 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                   " rows per mode); lower nmin";
             return TT_EINVAL;
         }
-    if (leaf_lds_bytes(D, s.bmax, s.maxtup, s.maxcpl, s.maxH) > 160 * 1024) {
+    const int lds_need = (s.cls == 1) ? leaf2_lds_bytes(D, s.bmax) : leaf_lds_bytes(D, s.bmax, s.maxtup, s.maxcpl, s.maxH);
+    if (lds_need > 160 * 1024) {
         err = "leaf block does not fit in LDS; lower nmin";
         return TT_EINVAL;
     }
