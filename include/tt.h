@@ -11,8 +11,11 @@
  *       sum_mu X x_1 C_1 ... x_mu A_mu ... x_d C_d = B
  *
  * Conventions shared by every entry point
- *   - d is the tensor order, 1 <= d <= 4; n[0..d-1] are the mode sizes
- *     (n[mu] >= 0; a zero-sized mode makes the call a no-op).
+ *   - d is the tensor order, 1 <= d <= 4 (solve_tri_tensor, its plans and
+ *     solve_general_tensor also take d = 5: the two adjacent modes with the
+ *     smallest product of sizes are merged, see tt_merge_modes_host); n[0..d-1]
+ *     are the mode sizes (n[mu] >= 0; a zero-sized mode makes the call a
+ *     no-op).
  *   - Tensors (B, X, G, dB, ...) are DEVICE pointers to float64 data in
  *     C order: the LAST mode is the fastest, element (i_1..i_d) sits at
  *     sum_mu i_mu * prod_{nu > mu} n[nu].  This is the reverse of the
@@ -379,6 +382,20 @@ int tt_schur_host(int n, const double* A, double* T, double* U);
  * No GPU is used.  Errors: TT_EINVAL (bad arguments, non-finite entries, no
  * convergence), TT_ESINGULAR (C singular to working precision). */
 int tt_qz_host(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z);
+
+/* Host-only merge of two adjacent modes (Algorithm 3, Sec. 2.2 for real
+ * quasi-triangular coefficients): with Ta (na x na, the slower mode) and Tb
+ * (nb x nb) upper quasi-triangular, the two terms of the merged mode act as
+ * A' = Ta (x) I_nb + I_na (x) Tb on the merged index i_a nb + i_b.  A perfect
+ * shuffle of the block rows of each 2x2 block of Ta makes A' block upper
+ * triangular with diagonal blocks of size at most 4; the 4x4 ones are brought
+ * to real Schur form.  Outputs (HOST, row-major, (na nb)^2 each): Tm upper
+ * quasi-triangular and V orthogonal with A' = V Tm V^T, and perm[r] = the
+ * merged index at position r of the shuffled order (na nb entries).  Order-5
+ * calls of solve_tri_tensor and solve_general_tensor merge the adjacent pair
+ * of modes with the smallest product of sizes this way.  na nb <= 4096.
+ * Errors: TT_EINVAL (sizes, NULL, structure), or that of the 4x4 Schur step. */
+int tt_merge_modes_host(int na, const double* Ta, int nb, const double* Tb, double* Tm, double* V, int* perm);
 
 #ifdef __cplusplus
 }

@@ -48,6 +48,7 @@ SYMBOLS = [
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
     "tt_copy_device", "tt_workspace_bytes", "solve_tri_tensor_noalloc",
     "solve_gsylv_tensor", "solve_gsylv_general_tensor", "tt_plan_create_gsylv", "tt_plan_create_gsylv_general",
+    "tt_merge_modes_host",
 ]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.tt_plan_create_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, ctypes.POINTER(Opts)]
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.tt_schur_host.argtypes = [ctypes.c_int, vp, vp, vp]
+        L.tt_merge_modes_host.argtypes = [ctypes.c_int, vp, ctypes.c_int, vp, vp, vp, vp]
         L.tt_qz_host.argtypes = [ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.tt_plan_coefficient_grads.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp]
         L.tt_plan_create_general_pair.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, vp,
@@ -280,6 +282,21 @@ def schur_host(A):
     U = np.zeros_like(A)
     _check(lib().tt_schur_host(n, A.ctypes.data, T.ctypes.data, U.ctypes.data))
     return T, U
+
+
+def merge_modes_host(Ta, Tb):
+    """Host merge of two adjacent modes (Algorithm 3, real quasi-triangular
+    case): returns (Tm, V, perm) with Ta (x) I + I (x) Tb = V Tm V^T, Tm upper
+    quasi-triangular, perm the perfect-shuffle order (numpy in, numpy out)."""
+    Ta = np.ascontiguousarray(np.asarray(Ta, dtype=np.float64))
+    Tb = np.ascontiguousarray(np.asarray(Tb, dtype=np.float64))
+    na, nb = Ta.shape[0], Tb.shape[0]
+    Tm = np.zeros((na * nb, na * nb))
+    V = np.zeros_like(Tm)
+    perm = np.zeros(na * nb, dtype=np.int32)
+    _check(lib().tt_merge_modes_host(na, Ta.ctypes.data, nb, Tb.ctypes.data, Tm.ctypes.data, V.ctypes.data,
+                                     perm.ctypes.data))
+    return Tm, V, perm
 
 
 def qz_host(A, C):

@@ -674,6 +674,117 @@ int plan_begin(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::vec
     return TT_OK;
 }
 
+// Single-problem plan of a triangular equation (Laplace-like, cls 0, or the
+// second class, cls 1) with host coefficients T (n[mu] x n[mu]) and
+// optional mode products applied to B before the solve (pre[mu]) and to its
+// result after it (post[mu]); empty matrices skip a mode, an empty post
+// vector skips the post-transforms.
+int pipeline_plan(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::vector<double>>& T,
+                  const std::vector<std::vector<double>>& pre, const std::vector<std::vector<double>>& post, int cls,
+                  const tt_opts* opts) {
+    int rc;
+    if ((rc = plan_begin(P, d, n, T, 0))) return rc;
+    P->sched.cls = cls;
+    P->kind = post.empty() ? KIND_PAIR : KIND_GENERAL;
+    if ((rc = finish_plan(P, opts ? opts->nmin : 0))) return rc;
+    const HostProblem& hp = P->sched.probs[0];
+    P->pre.assign((size_t)d, nullptr);
+    for (int mu = 0; mu < d; ++mu)
+        if (!pre[(size_t)mu].empty() && (rc = upload_matrix(P, pre[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
+    if (!post.empty()) {
+        P->post.assign((size_t)d, nullptr);
+        for (int mu = 0; mu < d; ++mu)
+            if (!post[(size_t)mu].empty() && (rc = upload_matrix(P, post[(size_t)mu], &P->post[(size_t)mu])))
+                return rc;
+    }
+    if ((rc = alloc_tensor(P, hp.N, &P->W))) return rc;
+    double f = 0;
+    const int lead = hp.D - hp.d_user;
+    for (int mu = 0; mu < hp.d_user; ++mu) {
+        if (!pre[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
+        if (mu < (int)post.size() && !post[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
+    }
+    P->pipe_flops = P->sched.stats.flops + f;
+    return TT_OK;
+}
+
+// row-major Kronecker product of two square matrices (empty = identity of
+// size q / p)
+std::vector<double> kron_sq(const std::vector<double>& A, int64_t p, const std::vector<double>& B, int64_t q) {
+    const int64_t m = p * q;
+    std::vector<double> K((size_t)(m * m), 0.0);
+    for (int64_t i = 0; i < p; ++i)
+        for (int64_t j = 0; j < p; ++j) {
+            const double a = A.empty() ? (i == j ? 1.0 : 0.0) : A[(size_t)(i * p + j)];
+            if (a == 0.0) continue;
+            for (int64_t k = 0; k < q; ++k)
+                for (int64_t l = 0; l < q; ++l) {
+                    const double b = B.empty() ? (k == l ? 1.0 : 0.0) : B[(size_t)(k * q + l)];
+                    K[(size_t)((i * q + k) * m + j * q + l)] = a * b;
+                }
+        }
+    return K;
+}
+
+std::vector<double> matmul_sq(const std::vector<double>& A, const std::vector<double>& B, int64_t m) {
+    std::vector<double> C((size_t)(m * m), 0.0);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t k = 0; k < m; ++k) {
+            const double a = A[(size_t)(i * m + k)];
+            if (a == 0.0) continue;
+            for (int64_t j = 0; j < m; ++j) C[(size_t)(i * m + j)] += a * B[(size_t)(k * m + j)];
+        }
+    return C;
+}
+
+// Order 5 (Sec. 2.4, Algorithm 3): the adjacent modes (a, a+1) with the
+// smallest n_a n_{a+1} are merged into one mode whose coefficient is
+// Tm = V^T (T_a (x) I + I (x) T_{a+1}) V (merge_modes: perfect shuffle and
+// real Schur forms of its 4x4 diagonal blocks); the merged mode's pre- and
+// post-transforms become V^T (pre_a (x) pre_{a+1}) and
+// (post_a (x) post_{a+1}) V.  T and pre (5 entries, empty = none) and post
+// (5 entries, or no entries for none) are replaced by their 4-mode versions
+// (post always has 4, the merged mode's V at least), n4 receives the merged
+// shape.
+int merge_order5(const int64_t* n, std::vector<std::vector<double>>& T, std::vector<std::vector<double>>& pre,
+                 std::vector<std::vector<double>>& post, int64_t* n4) {
+    int a = 0;
+    for (int k = 1; k < 4; ++k)
+        if (n[k] * n[k + 1] < n[a] * n[a + 1]) a = k;
+    const int64_t na = n[a], nb = n[a + 1], nm = na * nb;
+    if (nm > 2048) return fail(TT_EINVAL, "order 5: the two merged modes exceed 2048 rows together");
+    std::vector<double> Tm((size_t)(nm * nm)), V((size_t)(nm * nm));
+    std::vector<int> perm((size_t)nm);
+    std::string err;
+    if (nm > 0) {
+        int rc = merge_modes((int)na, T[(size_t)a].data(), (int)nb, T[(size_t)a + 1].data(), Tm.data(), V.data(),
+                             perm.data(), err);
+        if (rc) return fail(rc, err);
+    }
+    std::vector<double> Vt((size_t)(nm * nm));
+    for (int64_t i = 0; i < nm; ++i)
+        for (int64_t j = 0; j < nm; ++j) Vt[(size_t)(i * nm + j)] = V[(size_t)(j * nm + i)];
+    std::vector<double> pm = (pre[(size_t)a].empty() && pre[(size_t)a + 1].empty())
+                                 ? Vt
+                                 : matmul_sq(Vt, kron_sq(pre[(size_t)a], na, pre[(size_t)a + 1], nb), nm);
+    const bool hp = !post.empty() && !(post[(size_t)a].empty() && post[(size_t)a + 1].empty());
+    std::vector<double> qm = hp ? matmul_sq(kron_sq(post[(size_t)a], na, post[(size_t)a + 1], nb), V, nm) : V;
+    // the merged mode always has a post-transform (V)
+    std::vector<std::vector<double>> T4, pre4, post4;
+    for (int k = 0; k < 5; ++k) {
+        if (k == a + 1) continue;
+        const bool m = (k == a);
+        T4.push_back(m ? Tm : T[(size_t)k]);
+        pre4.push_back(m ? pm : pre[(size_t)k]);
+        post4.push_back(m ? qm : (post.empty() ? std::vector<double>() : post[(size_t)k]));
+        n4[(int)T4.size() - 1] = m ? nm : n[k];
+    }
+    T.swap(T4);
+    pre.swap(pre4);
+    post.swap(post4);
+    return TT_OK;
+}
+
 }  // namespace
 
 // Upper bound of the device bytes of one single-problem plan and call (see
@@ -939,8 +1050,48 @@ static double pipeline_flops(const HostProblem& hp, int products) {
     return f * products;
 }
 
+// Order 5 with device coefficients: Laplace-like (C NULL) or pair form (C:
+// exact C^{-1} reduction per mode), then the merge of two modes
+// (merge_order5) and a 4-mode plan with the merged mode's transforms.
+static int plan_order5(tt_plan_s* P, const int64_t* n, const double* const* T, const double* const* C,
+                       const tt_opts* opts) {
+    for (int mu = 0; mu < 5; ++mu)
+        if (n[mu] < 0 || n[mu] > (int64_t)1 << 30) return fail(TT_EINVAL, "mode size out of range");
+    if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "order 5 is FP64 only");
+    std::vector<std::vector<double>> A, Cm, Cinv, pre(5), post;
+    int rc;
+    if ((rc = fetch_matrices(5, n, T, A))) return rc;
+    for (int mu = 0; mu < 5; ++mu) {
+        std::vector<int32_t> bst;
+        std::string err;
+        if (partition_mode(n[mu], A[(size_t)mu].data(), 2, bst, err)) return fail(TT_EINVAL, err);
+    }
+    if (C) {
+        if ((rc = fetch_matrices(5, n, C, Cm))) return rc;
+        if ((rc = pair_reduce(5, n, A, Cm, Cinv))) return rc;
+        pre = Cinv;
+    }
+    int64_t n4[4];
+    if ((rc = merge_order5(n, A, pre, post, n4))) return rc;
+    return pipeline_plan(P, 4, n4, A, pre, post, 0, opts);
+}
+
 int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T,
                    const double* const* C, int trans, const tt_opts* opts) {
+    if (d == 5) {
+        if (!out) return fail(TT_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (!T || !n) return fail(TT_EINVAL, "NULL argument");
+        if (trans) return fail(TT_EINVAL, "adjoint plans support orders 1 to 4");
+        auto t0 = std::chrono::steady_clock::now();
+        std::unique_ptr<tt_plan_s> P(new tt_plan_s());
+        adopt_workspace(P.get(), opts);
+        int rc = plan_order5(P.get(), n, T, C, opts);
+        if (rc) return rc;
+        P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = P.release();
+        return TT_OK;
+    }
     if (!C) {
         if (!out) return fail(TT_EINVAL, "out is NULL");
         *out = nullptr;
@@ -998,6 +1149,43 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n, const double* 
     auto t0 = std::chrono::steady_clock::now();
     std::unique_ptr<tt_plan_s> P(new tt_plan_s());
     adopt_workspace(P.get(), opts);
+    if (d == 5) {
+        // host Schur of every mode, then the merge of two modes (order 5)
+        if (!n) return fail(TT_EINVAL, "n is NULL");
+        if (opts && opts->prec != TT_FP64) return fail(TT_EINVAL, "order 5 is FP64 only");
+        std::vector<std::vector<double>> T(5), U(5), pre(5), post(5);
+        std::vector<int> ni(5);
+        std::vector<const double*> ap(5);
+        std::vector<double*> tp(5), up(5);
+        for (int mu = 0; mu < 5; ++mu) {
+            if (n[mu] < 0 || n[mu] > 16384) return fail(TT_EINVAL, "mode size out of range");
+            if (!A_host[mu] && n[mu] > 0) return fail(TT_EINVAL, "coefficient pointer is NULL");
+            T[(size_t)mu].assign((size_t)(n[mu] * n[mu]), 0.0);
+            U[(size_t)mu].assign((size_t)(n[mu] * n[mu]), 0.0);
+            ni[(size_t)mu] = (int)n[mu];
+            ap[(size_t)mu] = A_host[mu];
+            tp[(size_t)mu] = T[(size_t)mu].data();
+            up[(size_t)mu] = U[(size_t)mu].data();
+        }
+        std::string err;
+        int rc = schur_real_many(5, ni.data(), ap.data(), tp.data(), up.data(), err);
+        if (rc) return fail(rc, err);
+        P->schur_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int mu = 0; mu < 5; ++mu) {
+            const int64_t m = n[mu];
+            pre[(size_t)mu].assign((size_t)(m * m), 0.0);
+            for (int64_t i = 0; i < m; ++i)
+                for (int64_t j = 0; j < m; ++j)
+                    pre[(size_t)mu][(size_t)(i * m + j)] = U[(size_t)mu][(size_t)(j * m + i)];
+            post[(size_t)mu] = U[(size_t)mu];
+        }
+        int64_t n4[4];
+        if ((rc = merge_order5(n, T, pre, post, n4))) return rc;
+        if ((rc = pipeline_plan(P.get(), 4, n4, T, pre, post, 0, opts))) return rc;
+        P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        *out = P.release();
+        return TT_OK;
+    }
     HostProblem probe;
     int rc = describe_problem(d, n, (d == 4) ? 4 : 3, probe);
     if (rc) return rc;
@@ -1130,37 +1318,11 @@ int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const dou
 static int gsylv_plan(tt_plan_s* P, int d, const int64_t* n, std::vector<std::vector<double>> T,
                       const std::vector<std::vector<double>>& pre, const std::vector<std::vector<double>>& post,
                       const tt_opts* opts) {
-    int rc;
     if (d == 1) {
         const int64_t m = n[0];
         for (int64_t i = 0; i < m; ++i) T[0][(size_t)(i * m + i)] += 1.0;
     }
-    if ((rc = plan_begin(P, d, n, T, 0))) return rc;
-    P->sched.cls = (d >= 3) ? 1 : 0;
-    P->kind = post.empty() ? KIND_PAIR : KIND_GENERAL;
-    if ((rc = finish_plan(P, opts ? opts->nmin : 0))) return rc;
-    const HostProblem& hp = P->sched.probs[0];
-    P->pre.assign((size_t)d, nullptr);
-    for (int mu = 0; mu < d; ++mu)
-        if (!pre[(size_t)mu].empty() && (rc = upload_matrix(P, pre[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
-    if (!post.empty()) {
-        P->post.assign((size_t)d, nullptr);
-        for (int mu = 0; mu < d; ++mu)
-            if (!post[(size_t)mu].empty() && (rc = upload_matrix(P, post[(size_t)mu], &P->post[(size_t)mu])))
-                return rc;
-    }
-    if ((rc = alloc_tensor(P, hp.N, &P->W))) return rc;
-    int products = 0;
-    for (const auto& m : pre) products += m.empty() ? 0 : 1;
-    for (const auto& m : post) products += m.empty() ? 0 : 1;
-    double f = 0;
-    const int lead = hp.D - hp.d_user;
-    for (int mu = 0; mu < hp.d_user; ++mu)
-        if (!pre[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
-    for (int mu = 0; mu < (int)post.size(); ++mu)
-        if (!post[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
-    P->pipe_flops = P->sched.stats.flops + f;
-    return TT_OK;
+    return pipeline_plan(P, d, n, T, pre, post, (d >= 3) ? 1 : 0, opts);
 }
 
 int tt_plan_create_gsylv(tt_plan* out, int d, const int64_t* n, const double* const* A, const double* C,
@@ -1635,6 +1797,20 @@ int tt_schur_host(int n, const double* A, double* T, double* U) {
     if (n < 0 || (n > 0 && (!A || !T || !U))) return fail(TT_EINVAL, "bad arguments");
     std::string err;
     int rc = schur_real(n, A, T, U, err);
+    if (rc) return fail(rc, err);
+    return TT_OK;
+}
+
+int tt_merge_modes_host(int na, const double* Ta, int nb, const double* Tb, double* Tm, double* V, int* perm) {
+    if (na < 0 || nb < 0 || (int64_t)na * nb > 4096) return fail(TT_EINVAL, "bad sizes");
+    if (na * nb > 0 && (!Ta || !Tb || !Tm || !V || !perm)) return fail(TT_EINVAL, "NULL argument");
+    for (int k = 0; k < 2; ++k) {
+        std::vector<int32_t> bst;
+        std::string err;
+        if (partition_mode(k ? nb : na, k ? Tb : Ta, 2, bst, err)) return fail(TT_EINVAL, err);
+    }
+    std::string err;
+    int rc = merge_modes(na, Ta, nb, Tb, Tm, V, perm, err);
     if (rc) return fail(rc, err);
     return TT_OK;
 }

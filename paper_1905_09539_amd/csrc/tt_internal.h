@@ -219,6 +219,8 @@ hipError_t launch_f32_to_f64(const float* x, double* y, int64_t n, hipStream_t s
 int qz_real(int n, const double* A, const double* C, double* S, double* T, double* Q, double* Z,
             std::string& err);
 int schur_real(int n, const double* A, double* T, double* U, std::string& err);
+int merge_modes(int na, const double* Ta, int nb, const double* Tb, double* Tm, double* V, int* perm,
+                std::string& err);
 int schur_real_many(int count, const int* n, const double* const* A, double* const* T, double* const* U,
                     std::string& err);
 

@@ -516,4 +516,113 @@ int schur_real_many(int count, const int* n, const double* const* A, double* con
     return TT_OK;
 }
 
+// Merged coefficient of two adjacent modes (Sec. 2.2, Algorithm 3's merge
+// in the real quasi-triangular case).  With the outer (slower) mode a and the
+// inner mode b, the two terms X x_a A_a + X x_b A_b act on the merged index
+// m = i_a n_b + i_b as
+//     A' = A_a (x) I_b + I_a (x) A_b,
+// which is block upper triangular but not quasi-triangular where A_a has a
+// 2x2 block (j, j+1): its (j+1, j) block is A_a[j+1][j] I.  A perfect shuffle
+// of block rows and columns j, j+1 (order (j, 0), (j+1, 0), (j, 1), ...) makes
+// the region block upper triangular with 2x2 diagonal blocks, 4x4 where A_b
+// has a 2x2 block too (Sec. 2.2, the example after eq. (2.9)).  A 4x4 block
+// is brought to real Schur form by the host QR iteration; a 2x2 block is
+// already a valid diagonal block.  Result: A' = V Tm V^T with V = P Q
+// orthogonal (permutation times block-diagonal orthogonal) and Tm upper
+// quasi-triangular.  perm[r] = the merged index at position r of the
+// shuffled order.  All matrices row-major, na*nb squared.
+int merge_modes(int na, const double* Ta, int nb, const double* Tb, double* Tm, double* V, int* perm,
+                std::string& err) {
+    const int nm = na * nb;
+    const size_t NN = (size_t)nm * (size_t)nm;
+    std::vector<double> A(NN, 0.0);
+    for (int ia = 0; ia < na; ++ia)
+        for (int ib = 0; ib < nb; ++ib) {
+            const int r = ia * nb + ib;
+            for (int ja = 0; ja < na; ++ja) A[(size_t)r * nm + (size_t)(ja * nb + ib)] += Ta[ia * na + ja];
+            for (int jb = 0; jb < nb; ++jb) A[(size_t)r * nm + (size_t)(ia * nb + jb)] += Tb[ib * nb + jb];
+        }
+    // perfect shuffle of the block pairs of A_a's 2x2 blocks
+    std::vector<int> p;
+    p.reserve((size_t)nm);
+    for (int ja = 0; ja < na;) {
+        const bool two = ja + 1 < na && Ta[(ja + 1) * na + ja] != 0.0;
+        if (two) {
+            for (int ib = 0; ib < nb; ++ib) {
+                p.push_back(ja * nb + ib);
+                p.push_back((ja + 1) * nb + ib);
+            }
+            ja += 2;
+        } else {
+            for (int ib = 0; ib < nb; ++ib) p.push_back(ja * nb + ib);
+            ja += 1;
+        }
+    }
+    std::vector<double> Ap(NN);
+    for (int r = 0; r < nm; ++r)
+        for (int c = 0; c < nm; ++c) Ap[(size_t)r * nm + c] = A[(size_t)p[r] * nm + p[c]];
+    // diagonal blocks of the shuffled matrix and their orthogonal factors
+    std::vector<double> Q(NN, 0.0);
+    std::vector<int> bstart;
+    for (int r = 0; r < nm;) {
+        int sz = 1;
+        const int ia = p[r] / nb, ib = p[r] % nb;
+        const bool twoa = ia + 1 < na && Ta[(ia + 1) * na + ia] != 0.0 && p[r] == ia * nb + ib &&
+                          r + 1 < nm && p[r + 1] == (ia + 1) * nb + ib;
+        const bool twob = ib + 1 < nb && Tb[(ib + 1) * nb + ib] != 0.0;
+        if (twoa) sz = twob ? 4 : 2;
+        else sz = twob ? 2 : 1;
+        bstart.push_back(r);
+        if (sz == 4) {
+            double B4[16], T4[16], U4[16];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) B4[i * 4 + j] = Ap[(size_t)(r + i) * nm + r + j];
+            std::string e2;
+            const int rc = schur_real(4, B4, T4, U4, e2);
+            if (rc) {
+                err = "merge: real Schur form of a 4x4 diagonal block failed: " + e2;
+                return rc;
+            }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) Q[(size_t)(r + i) * nm + r + j] = U4[i * 4 + j];
+        } else {
+            for (int i = 0; i < sz; ++i) Q[(size_t)(r + i) * nm + r + i] = 1.0;
+        }
+        r += sz;
+    }
+    bstart.push_back(nm);
+    // Tm = Q^T Ap Q blockwise (Q block diagonal); entries below the block
+    // diagonal are zero, a 4x4 diagonal block takes its Schur form exactly
+    std::fill(Tm, Tm + NN, 0.0);
+    const int nblk = (int)bstart.size() - 1;
+    for (int bi = 0; bi < nblk; ++bi) {
+        const int r0 = bstart[(size_t)bi], r1 = bstart[(size_t)bi + 1];
+        for (int bj = bi; bj < nblk; ++bj) {
+            const int c0 = bstart[(size_t)bj], c1 = bstart[(size_t)bj + 1];
+            for (int i = r0; i < r1; ++i)
+                for (int j = c0; j < c1; ++j) {
+                    double acc = 0.0;
+                    for (int k = r0; k < r1; ++k)
+                        for (int l = c0; l < c1; ++l)
+                            acc += Q[(size_t)k * nm + i] * Ap[(size_t)k * nm + l] * Q[(size_t)l * nm + j];
+                    Tm[(size_t)i * nm + j] = acc;
+                }
+        }
+        if (r1 - r0 == 4) {
+            double B4[16], T4[16], U4[16];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) B4[i * 4 + j] = Ap[(size_t)(r0 + i) * nm + r0 + j];
+            std::string e2;
+            (void)schur_real(4, B4, T4, U4, e2);
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) Tm[(size_t)(r0 + i) * nm + r0 + j] = T4[i * 4 + j];
+        }
+    }
+    // V = P Q: row p[r] of V is row r of Q
+    for (int r = 0; r < nm; ++r)
+        for (int c = 0; c < nm; ++c) V[(size_t)p[r] * nm + c] = Q[(size_t)r * nm + c];
+    for (int r = 0; r < nm; ++r) perm[r] = p[r];
+    return TT_OK;
+}
+
 }  // namespace tt
