@@ -127,6 +127,14 @@ def _pair_residual(A, C, X, B):
     return float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
 
 
+class _Progress(dict):
+    """Result dict that reports each finished workload on stderr."""
+
+    def __setitem__(self, key, value):
+        super().__setitem__(key, value)
+        print(f"bench: {key} {json.dumps(value)}", file=sys.stderr, flush=True)
+
+
 def extras(args):
     """The other workloads of the method, timed the same way (inputs resident
     in HBM, HIP events on the caller's stream)."""
@@ -134,7 +142,7 @@ def extras(args):
 
     import paper_1905_09539_amd as tt
     import tt_inputs as ti
-    out = {}
+    out = _Progress()
     steps = max(2, args.steps // 4)
 
     # dense coefficients, d = 3, n = 512 (Algorithm 1: transforms + solve)
@@ -164,16 +172,21 @@ def extras(args):
     r64 = _residual(Ad, X64, B)
     del plan64
     torch.cuda.empty_cache()
-    planmp = tt.Plan(p["A"], B.shape, general=True, prec=tt.TT_MP_FP32, tol=1e-13)
-    msmp = _timed(lambda: planmp.solve(B, Xmp), 2, 1)
-    planmp.status()
-    info = planmp.info()
-    rmp = _residual(Ad, Xmp, B)
-    diff = float(torch.linalg.vector_norm(Xmp - X64) / torch.linalg.vector_norm(X64))
-    out["mixed_768"] = {"ms_fp64": ms64, "ms_mp_fp32": msmp, "speedup": ms64 / msmp,
-                        "iterations": info["iterations"], "last_ratio": info["ratio"],
-                        "residual_fp64": r64, "residual_mp": rmp, "rel_diff_mp_vs_fp64": diff}
-    del planmp, B, Ad, X64, Xmp, p
+    out["mixed_768"] = {"ms_fp64": ms64, "residual_fp64": r64}
+    for name, prec in (("fp32", tt.TT_MP_FP32), ("bf16", tt.TT_MP_BF16)):
+        planmp = tt.Plan(p["A"], B.shape, general=True, prec=prec, tol=1e-13)
+        msmp = _timed(lambda: planmp.solve(B, Xmp), 2, 1)
+        planmp.status()
+        info = planmp.info()
+        rmp = _residual(Ad, Xmp, B)
+        diff = float(torch.linalg.vector_norm(Xmp - X64) / torch.linalg.vector_norm(X64))
+        out["mixed_768"].update({f"ms_mp_{name}": msmp, f"speedup_{name}": ms64 / msmp,
+                                 f"iterations_{name}": info["iterations"], f"last_ratio_{name}": info["ratio"],
+                                 f"residual_mp_{name}": rmp, f"rel_diff_{name}_vs_fp64": diff})
+        del planmp
+        torch.cuda.empty_cache()
+    out["mixed_768"] = out["mixed_768"]
+    del B, Ad, X64, Xmp, p
     torch.cuda.empty_cache()
 
     # pair form, d = 4: (96, 96, 96, 96) and the merge case (1024, 1024, 8, 8)
@@ -207,6 +220,44 @@ def extras(args):
     del plan, Ad, Cd, B, X, p
     torch.cuda.empty_cache()
 
+    # second operator class (eq. (3.1)), triangular, d = 3 and d = 4
+    for shp in [(384, 384, 384), (96, 96, 96, 96)]:
+        p = ti.gsylv_tri(shp, seed=args.seed)
+        A = [torch.from_numpy(a).cuda() for a in p["A"]]
+        C = torch.from_numpy(p["C"]).cuda()
+        B = torch.from_numpy(p["B"]).cuda()
+        X = torch.empty_like(B)
+        plan = tt.Plan(A, B.shape, C=C, gsylv=True)
+        ms = _timed(lambda: plan.solve(B, X), steps, 1)
+        plan.status()
+        R = B - torch.movedim(torch.tensordot(A[0], X, dims=([1], [0])), 0, 0)
+        Y = X
+        for nu in range(len(shp)):
+            Y = torch.movedim(torch.tensordot(C if nu == 0 else A[nu], Y, dims=([1], [nu])), 0, nu)
+        R -= Y
+        out["gsylv_" + "x".join(str(x) for x in shp)] = {
+            "ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
+            "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
+        del plan, A, C, B, X, p, R, Y
+        torch.cuda.empty_cache()
+
+    # order 5 (Laplace-like, merged pair of modes), (40, 40, 40, 40, 40)
+    shp = (40, 40, 40, 40, 40)
+    p = ti.laplace_tri(shp, seed=args.seed)
+    T = [torch.from_numpy(t).cuda() for t in p["T"]]
+    B = torch.from_numpy(p["B"]).cuda()
+    X = torch.empty_like(B)
+    plan = tt.Plan(T, B.shape)
+    ms = _timed(lambda: plan.solve(B, X), steps, 1)
+    plan.status()
+    R = B.clone()
+    for mu in range(5):
+        R -= torch.movedim(torch.tensordot(T[mu], X, dims=([1], [mu])), 0, mu)
+    out["order5_40"] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
+                        "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
+    del plan, T, B, X, p, R
+    torch.cuda.empty_cache()
+
     # adjoint: 64 uneven d = 3 problems, forward + backward (dB and dT)
     probs = ti.uneven_batch(64, 32, 192, seed=args.seed)
     T = [[torch.from_numpy(t).cuda() for t in q["T"]] for q in probs]
@@ -231,7 +282,7 @@ def extras(args):
     planb.status()
     out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "ms_backward_plan": msbp,
                               "forward_flops": plan.flops}
-    return out
+    return dict(out)
 
 
 def main():

@@ -57,7 +57,9 @@ typedef enum {
 typedef enum {
     TT_FP64 = 0,        /* all arithmetic in float64                         */
     TT_MP_FP32 = 1,     /* updates/transforms in FP32, FP64 refinement       */
-    TT_MP_BF16 = 2      /* updates/transforms in BF16 MFMA, FP64 refinement  */
+    TT_MP_BF16 = 2      /* updates/transforms as three-term BF16 MFMA
+                           products (six per pair, FP32 accumulation),
+                           FP64 refinement                                   */
 } tt_prec;
 
 typedef struct {
@@ -119,8 +121,9 @@ const char* tt_last_error(void);
  *          are formed on the host, the products run on the GPU.
  *   B:     right-hand side (device, read only unless X == B).
  *   X:     solution (device); X may alias B (FP64 only).
- *   opts->prec: TT_MP_FP32 (Laplace-like form only) solves with FP32-MFMA
- *          recursion updates and refines in FP64 with the residual
+ *   opts->prec: TT_MP_FP32 or TT_MP_BF16 (Laplace-like form only) solves
+ *          with FP32-MFMA (or split-BF16 MFMA) recursion updates and FP64
+ *          leaves, and refines in FP64 with the residual
  *          B - sum_mu X x_mu T_mu; X must not alias B.
  * Errors: TT_EINVAL (d, n, NULL pointer, T not quasi-triangular, C not
  * triangular), TT_ESINGULAR (zero pivot or non-finite result; X content is
@@ -161,8 +164,10 @@ int solve_tri_tensor_noalloc(int d, const int64_t* n, const double* const* T,
  * GPU, the triangular solve, and X = X~ x_1 U_1 ... x_d U_d on the GPU.
  *   A_host[mu]: HOST pointers to dense row-major n[mu] x n[mu] matrices.
  *   B, X: device tensors; X may alias B.
- * opts->prec selects FP64 or TT_MP_FP32: transforms and recursion updates in
- * FP32 MFMA with FP32 accumulation, leaf solves (with their divisions by
+ * opts->prec selects FP64, TT_MP_FP32 or TT_MP_BF16: transforms and recursion
+ * updates in FP32 MFMA (TT_MP_BF16: each FP64 operand split into three BF16
+ * terms, six BF16 MFMA products per pair) with FP32 accumulation, leaf
+ * solves (with their divisions by
  * eigenvalue sums) in FP64, and FP64 iterative refinement with the residual
  * B - sum_mu X x_mu A_mu of the dense A_mu (X must not alias B then).
  * opts->info[0..2] report the refinement iterations, the last ratio
@@ -256,7 +261,8 @@ int solve_backward_batched(int count, const int* d, const int64_t* const* n,
  *     Laplace-like form, plus 2 n_mu N per mode product of the pair form
  *     (d products) and of the dense-coefficient pipeline (2d products).
  *   Batched and adjoint plans are FP64 only; tt_plan_create with
- *     opts->prec = TT_MP_FP32 (Laplace-like form) refines in FP64.
+ *     opts->prec = TT_MP_FP32 or TT_MP_BF16 (Laplace-like form) refines
+ *     in FP64.
  * ------------------------------------------------------------------------- */
 typedef struct tt_plan_s* tt_plan;
 
@@ -265,7 +271,8 @@ int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T
 /* Dense coefficients (Algorithm 1): the host Schur decompositions happen
  * here; tt_plan_solve then runs B x_mu U_mu^T, the triangular solve and
  * x_mu U_mu on the GPU (and the refinement loop when opts->prec is
- * TT_MP_FP32).  A_host: HOST pointers to row-major n[mu] x n[mu] matrices. */
+ * TT_MP_FP32 or TT_MP_BF16).  A_host: HOST pointers to row-major n[mu] x n[mu]
+ * matrices. */
 int tt_plan_create_general(tt_plan* out, int d, const int64_t* n,
                            const double* const* A_host, const tt_opts* opts);
 

@@ -159,7 +159,8 @@ def solve_tri(T, B, C=None, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10
     C given, the pair form sum_mu X x_1 C_1 .. x_mu T_mu .. x_d C_d = B.
     T, C: lists of n_mu x n_mu float64 CUDA tensors (T upper quasi-triangular,
     C upper triangular); B: float64 CUDA tensor of shape (n_1, ..., n_d).
-    prec=TT_MP_FP32: FP32-MFMA updates with FP64 refinement (info, if a dict,
+    prec=TT_MP_FP32 (TT_MP_BF16): FP32-MFMA (split-BF16 MFMA) updates with
+    FP64 leaves and FP64 refinement (info, if a dict,
     receives iterations and the last correction ratio).  workspace: an
     optional CUDA tensor of at least workspace_bytes(B.shape, prec) bytes
     from which every device buffer of the call is carved."""

@@ -567,7 +567,8 @@ int apply_chain(tt_plan_s* P, const double* src, double* fin, double* other, con
 //   TRI:     copy, triangular solve (adjoint plans reverse the order);
 //   PAIR:    X = B x_mu C_mu^{-1} (all modes), triangular solve in X;
 //   GENERAL: B~ = B x_mu U_mu^T, triangular solve, X = X~ x_mu U_mu.
-// lp = 1 runs the recursion updates and the transforms in FP32 MFMA.
+// lp = 1 runs the recursion updates and the transforms in FP32 MFMA, lp = 2
+// in three-term BF16 MFMA with FP32 accumulation; the leaves stay FP64.
 int run_pipeline(tt_plan_s* P, const double* B, double* X, int lp, hipStream_t st) {
     if (P->kind == KIND_TRI) {
         int rc = prepare_inputs(P, &B, &X, st);
@@ -602,7 +603,8 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
     P->last_info[1] = 0;
     if (hp.N == 0) return TT_OK;
     if (B == X) return fail(TT_EINVAL, "mixed precision needs X distinct from B (B enters every residual)");
-    int rc = run_pipeline(P, B, X, 1, st);
+    const int lp = (P->prec == TT_MP_BF16) ? 2 : 1;
+    int rc = run_pipeline(P, B, X, lp, st);
     if (rc) return rc;
     const int nb = sumsq_blocks();
     for (int it = 1; it <= P->max_iter; ++it) {
@@ -613,7 +615,7 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
             TT_HIP_CHECK(launch_modeprod(X, P->R, P->R, P->Adev[(size_t)mu], L, (int)nm, (int)nm, Rr, -1.0, 1.0, 0,
                                          st));
         }
-        if ((rc = run_pipeline(P, P->R, P->R, 1, st))) return rc;
+        if ((rc = run_pipeline(P, P->R, P->R, lp, st))) return rc;
         TT_HIP_CHECK(launch_axpy(X, P->R, 1.0, hp.N, st));
         TT_HIP_CHECK(launch_sumsq2(P->R, X, hp.N, P->part, st));
         TT_HIP_CHECK(hipMemcpyAsync(P->part_host.data(), P->part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
@@ -635,8 +637,7 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
 int setup_refinement(tt_plan_s* P, const std::vector<std::vector<double>>& A, const tt_opts* opts) {
     P->prec = opts ? opts->prec : TT_FP64;
     if (P->prec == TT_FP64) return TT_OK;
-    if (P->prec == TT_MP_BF16) return fail(TT_EINVAL, "BF16 mixed precision is not available (use TT_MP_FP32)");
-    if (P->prec != TT_MP_FP32) return fail(TT_EINVAL, "unknown precision");
+    if (P->prec != TT_MP_FP32 && P->prec != TT_MP_BF16) return fail(TT_EINVAL, "unknown precision");
     if (P->count != 1 || P->trans) return fail(TT_EINVAL, "mixed precision needs a single, non-adjoint problem");
     P->tol = opts->tol > 0 ? opts->tol : 1e-13;
     P->max_iter = opts->max_iter > 0 ? opts->max_iter : 10;

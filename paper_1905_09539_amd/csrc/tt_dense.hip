@@ -11,6 +11,7 @@
 //
 // A tensor of shape (n_1..n_d) in C order is viewed, for mode mu, as
 // [L][n_mu][R] with L = prod_{nu<mu} n_nu and R = prod_{nu>mu} n_nu.
+#include "tt_bf16.h"
 #include "tt_internal.h"
 
 namespace tt {
@@ -23,45 +24,64 @@ constexpr int kDRow = 80;    // LDS row pitch (doubles)
 constexpr int kDThreads = 256;
 static_assert(kDT == kGramTile && kDKC == kGramKC, "Gram job planning assumes the kernel's tile and K chunk");
 
-// 2x2 blocks of 16x16x4 MFMA per wave over one K chunk.  LP = false:
-// v_mfma_f64_16x16x4f64; LP = true: operands rounded to FP32 and
-// v_mfma_f32_16x16x4f32 with FP32 accumulation.  Lane layout: A[i][k] from
-// lane 16k + i, B[k][j] from lane 16k + j; result element v of lane 16 g + j
-// is D[4 v + g][j] (FP64) or D[4 g + v][j] (FP32).
-template <bool LP>
+// 2x2 blocks of 16x16x4 MFMA per wave over one K chunk.  LP = 0:
+// v_mfma_f64_16x16x4f64; LP = 1: operands rounded to FP32 and
+// v_mfma_f32_16x16x4f32 with FP32 accumulation; LP = 2: operands split into
+// three BF16 terms and six-term products on v_mfma_f32_16x16x16_bf16 (one
+// 16x16x16 step per chunk, tt_bf16.h).  Lane layout: A[i][k] from lane
+// 16k + i, B[k][j] from lane 16k + j (16x16x16: lane 16 (k / 4) + i holds
+// k % 4 of four); result element v of lane 16 g + j is D[4 v + g][j] (FP64)
+// or D[4 g + v][j] (FP32 accumulation).
+template <int LP>
 struct MAcc {
-    typedef double type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct MAcc<true> {
     typedef float type __attribute__((ext_vector_type(4)));
 };
+template <>
+struct MAcc<0> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
 
-template <bool LP>
+template <int LP>
 __device__ inline int mrow(int v, int g) {
     return LP ? 4 * g + v : 4 * v + g;
 }
 
-template <bool LP>
+template <int LP>
 __device__ inline void mfma_chunk16(const double* As, const double* Bs, int wr, int wc, int li, int lk,
                                     typename MAcc<LP>::type (&acc)[2][2]) {
+    if constexpr (LP == 2) {
+        const double* A0 = As + 4 * lk * kDRow;
+        const double* B0 = Bs + 4 * lk * kDRow;
+        Split4 a[2], b[2];
 #pragma unroll
-    for (int kk = 0; kk < kDKC; kk += 4) {
-        const double* Ak = As + (kk + lk) * kDRow;
-        const double* Bk = Bs + (kk + lk) * kDRow;
-        double a0 = Ak[wr + li], a1 = Ak[wr + 16 + li];
-        double b0 = Bk[wc + li], b1 = Bk[wc + 16 + li];
-        if constexpr (LP) {
-            const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
-            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb1, acc[1][1], 0, 0, 0);
-        } else {
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+            const int r = wr + 16 * i + li, c = wc + 16 * i + li;
+            a[i] = split4(A0[r], A0[kDRow + r], A0[2 * kDRow + r], A0[3 * kDRow + r]);
+            b[i] = split4(B0[c], B0[kDRow + c], B0[2 * kDRow + c], B0[3 * kDRow + c]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16x6(a[i], b[j], acc[i][j]);
+    } else {
+#pragma unroll
+        for (int kk = 0; kk < kDKC; kk += 4) {
+            const double* Ak = As + (kk + lk) * kDRow;
+            const double* Bk = Bs + (kk + lk) * kDRow;
+            double a0 = Ak[wr + li], a1 = Ak[wr + 16 + li];
+            double b0 = Bk[wc + li], b1 = Bk[wc + 16 + li];
+            if constexpr (LP == 1) {
+                const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa1, fb1, acc[1][1], 0, 0, 0);
+            } else {
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
         }
     }
 }
@@ -84,7 +104,7 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nblocks) {
 //   R == 1: MFMA rows = l (X rows, contiguous along j), columns = i.
 // Grid: row tiles x column tiles, flattened, renumbered per XCD.
 // ---------------------------------------------------------------------------
-template <bool LP>
+template <int LP>
 __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __restrict__ X, double* Y,
                                                              const double* Z,
                                                              const double* __restrict__ M, int64_t L,
@@ -414,11 +434,14 @@ hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const do
     const int64_t cols = (R > 1) ? L * R : nout;
     const int64_t tiles = ((rows + kDT - 1) / kDT) * ((cols + kDT - 1) / kDT);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    if (lp)
-        hipLaunchKernelGGL(modeprod_kernel<true>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+    if (lp == 2)
+        hipLaunchKernelGGL(modeprod_kernel<2>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+                           nout, R, alpha, beta);
+    else if (lp == 1)
+        hipLaunchKernelGGL(modeprod_kernel<1>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
                            nout, R, alpha, beta);
     else
-        hipLaunchKernelGGL(modeprod_kernel<false>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+        hipLaunchKernelGGL(modeprod_kernel<0>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
                            nout, R, alpha, beta);
     return hipGetLastError();
 }

@@ -6,6 +6,7 @@
 //                   on FP64 MFMA (v_mfma_f64_16x16x4f64).
 #include <algorithm>
 
+#include "tt_bf16.h"
 #include "tt_internal.h"
 
 namespace tt {
@@ -55,20 +56,22 @@ __device__ inline int64_t pencil_col_offset(const UpdDesc& t, int c) {
     return off;
 }
 
-// LP = false: FP64 MFMA.  LP = true: operands rounded to FP32 and
-// v_mfma_f32_16x16x4f32 with FP32 accumulation (the low-precision updates of
-// mixed-precision refinement); its result element v of lane 16 g + j is
+// LP = 0: FP64 MFMA.  LP = 1: operands rounded to FP32 and
+// v_mfma_f32_16x16x4f32 with FP32 accumulation; LP = 2: operands split into
+// three BF16 terms, six-term products on v_mfma_f32_16x16x16_bf16 with FP32
+// accumulation (tt_bf16.h).  LP 1 and 2 are the low-precision updates of
+// mixed-precision refinement; their result element v of lane 16 g + j is
 // D[4 g + v][j] instead of the FP64 instruction's D[4 v + g][j].
-template <bool LP>
+template <int LP>
 struct MfmaAcc {
-    typedef double type __attribute__((ext_vector_type(4)));
-};
-template <>
-struct MfmaAcc<true> {
     typedef float type __attribute__((ext_vector_type(4)));
 };
+template <>
+struct MfmaAcc<0> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
 
-template <bool LP>
+template <int LP>
 __device__ inline int mfma_row(int v, int g) {
     return LP ? 4 * g + v : 4 * v + g;
 }
@@ -78,9 +81,26 @@ __device__ inline int mfma_row(int v, int g) {
 // pitch kLdsRow or (ARK / BRK) as [row][k] with pitch kRkRow (odd, so the
 // sixteen rows a lane group reads fall in distinct banks).
 constexpr int kRkRow = kKC + 1;
-template <bool LP, bool ARK, bool BRK>
+template <int LP, bool ARK, bool BRK>
 __device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, int wc, int li, int lk,
                                     typename MfmaAcc<LP>::type (&acc)[2][2]) {
+    if constexpr (LP == 2) {
+        // one 16x16x16 step: this lane's K values are 4 lk .. 4 lk + 3
+        auto A = [&](int r, int k) { return ARK ? As[r * kRkRow + k] : As[k * kLdsRow + r]; };
+        auto B = [&](int c, int k) { return BRK ? Bs[c * kRkRow + k] : Bs[k * kLdsRow + c]; };
+        const int k0 = 4 * lk;
+        Split4 a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = wr + 16 * i + li, c = wc + 16 * i + li;
+            a[i] = split4(A(r, k0), A(r, k0 + 1), A(r, k0 + 2), A(r, k0 + 3));
+            b[i] = split4(B(c, k0), B(c, k0 + 1), B(c, k0 + 2), B(c, k0 + 3));
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = mfma_bf16x6(a[i], b[j], acc[i][j]);
+    } else {
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 4) {
         const int k = kk + lk;
@@ -88,7 +108,7 @@ __device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, 
         const double a1 = ARK ? As[(wr + 16 + li) * kRkRow + k] : As[k * kLdsRow + wr + 16 + li];
         const double b0 = BRK ? Bs[(wc + li) * kRkRow + k] : Bs[k * kLdsRow + wc + li];
         const double b1 = BRK ? Bs[(wc + 16 + li) * kRkRow + k] : Bs[k * kLdsRow + wc + 16 + li];
-        if constexpr (LP) {
+        if constexpr (LP == 1) {
             const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb1, acc[0][1], 0, 0, 0);
@@ -100,6 +120,7 @@ __device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, 
             acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
+    }
     }
 }
 
@@ -139,7 +160,7 @@ __device__ inline void k_pipeline(int nchunk, Load&& load, Stage&& stage, Comput
 // leave 3/4 of its MFMA rows idle): 16 target rows x 256 pencil columns, each
 // wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
 // the target rows; right path (fastest mode): MFMA rows are pencil columns.
-template <bool LP>
+template <int LP>
 __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
                                 gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
                                 bool right, bool store, const gdouble* B0, double sgn, double* As, double* Bs,
@@ -208,6 +229,19 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
         __syncthreads();
     };
     auto compute = [&]() {
+        if constexpr (LP == 2) {
+            // one 16x16x16 step per block: K values 4 lk .. 4 lk + 3 of this lane
+            const int k0 = 4 * lk;
+            const Split4 ts = split4(As[k0 * kTRow + li], As[(k0 + 1) * kTRow + li], As[(k0 + 2) * kTRow + li],
+                                     As[(k0 + 3) * kTRow + li]);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int c = wave * 64 + b * 16 + li;
+                auto xv = [&](int k) { return right ? Bs[c * kCRow + k] : Bs[k * kWRow + c]; };
+                const Split4 xs = split4(xv(k0), xv(k0 + 1), xv(k0 + 2), xv(k0 + 3));
+                acc[b] = right ? mfma_bf16x6(xs, ts, acc[b]) : mfma_bf16x6(ts, xs, acc[b]);
+            }
+        } else {
 #pragma unroll
         for (int kk = 0; kk < kKC; kk += 4) {
             const double tv = As[(kk + lk) * kTRow + li];
@@ -215,7 +249,7 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
             for (int b = 0; b < 4; ++b) {
                 const int c = wave * 64 + b * 16 + li;
                 const double xv = right ? Bs[c * kCRow + kk + lk] : Bs[(kk + lk) * kWRow + c];
-                if constexpr (LP) {
+                if constexpr (LP == 1) {
                     const float ft = (float)tv, fx = (float)xv;
                     acc[b] = right ? __builtin_amdgcn_mfma_f32_16x16x4f32(fx, ft, acc[b], 0, 0, 0)
                                    : __builtin_amdgcn_mfma_f32_16x16x4f32(ft, fx, acc[b], 0, 0, 0);
@@ -224,6 +258,7 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
                                    : __builtin_amdgcn_mfma_f64_16x16x4f64(tv, xv, acc[b], 0, 0, 0);
                 }
             }
+        }
         }
     };
     gload(ra, rb, 0);
@@ -247,7 +282,7 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
         }
 }
 
-template <bool LP>
+template <int LP>
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))) void upd_kernel(const UpdDesc* __restrict__ tasks,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t first,
@@ -455,11 +490,14 @@ hipError_t launch_update(int D, const UpdDesc* tasks, const WorkItem* items, int
             if (2 * u + leaf <= cu_lds && u > stat && u <= 64 * 1024) pad = (size_t)(u - stat);
         }
     }
-    if (lp)
-        hipLaunchKernelGGL(upd_kernel<true>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
+    if (lp == 2)
+        hipLaunchKernelGGL(upd_kernel<2>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
+                           probs, D);
+    else if (lp == 1)
+        hipLaunchKernelGGL(upd_kernel<1>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
                            probs, D);
     else
-        hipLaunchKernelGGL(upd_kernel<false>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
+        hipLaunchKernelGGL(upd_kernel<0>, dim3((unsigned)count), dim3(kUpdThreads), pad, st, tasks, items, first,
                            probs, D);
     return hipGetLastError();
 }

@@ -82,8 +82,8 @@ def test_dense_256_full_oracle():
 
 
 def test_mixed_768_full_oracle():
-    """d = 3, n = 768 (eigenvalue sums in [3, 6]): FP64 and FP32-MFMA
-    refinement, both against the oracle's 768^3 triangular solve."""
+    """d = 3, n = 768 (eigenvalue sums in [3, 6]): FP64, FP32-MFMA and
+    split-BF16 refinement, all against the oracle's 768^3 triangular solve."""
     n = 768
     p = ti.laplace_tri((n, n, n), seed=1, bumps="every8")
     T = [dev(t) for t in p["T"]]
@@ -93,16 +93,22 @@ def test_mixed_768_full_oracle():
     print("case tri 768^3 mp fp32", flush=True)
     info = {}
     Xmp = host(tt().solve_tri(T, B, prec=tt().TT_MP_FP32, tol=1e-13, info=info))
+    print("case tri 768^3 mp bf16", flush=True)
+    infob = {}
+    Xbf = host(tt().solve_tri(T, B, prec=tt().TT_MP_BF16, tol=1e-13, info=infob))
     del B, T
     torch.cuda.empty_cache()
     print("case tri 768^3 oracle", flush=True)
     Xo = oracle.lap_solve(p["T"], p["B"])
     e64, m64 = errs(X64, Xo)
     emp, mmp = errs(Xmp, Xo)
+    ebf, mbf = errs(Xbf, Xo)
     print(f"768^3 fp64: normwise {e64:.3e} max-abs {m64:.3e}; mp fp32 ({info['iterations']} it): "
-          f"normwise {emp:.3e} max-abs {mmp:.3e}", flush=True)
+          f"normwise {emp:.3e} max-abs {mmp:.3e}; mp bf16 ({infob['iterations']} it): "
+          f"normwise {ebf:.3e} max-abs {mbf:.3e}", flush=True)
     assert e64 <= TOL and m64 <= TOL
     assert emp <= TOL and mmp <= TOL
+    assert ebf <= TOL and mbf <= TOL
 
 
 def test_mixed_dense_256_full_oracle():

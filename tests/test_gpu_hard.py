@@ -68,17 +68,20 @@ def test_benign_variant_vs_long_double(n):
     assert e <= 1e-12
 
 
-def test_hard_variant_mixed_precision():
-    """FP32-MFMA refinement on the hard variant: kappa * u_fp32 ~ 0.06 < 1, so
-    refinement still contracts (slowly); the refined X is compared with the
-    long-double oracle against the same kappa-based bound as FP64."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_hard_variant_mixed_precision(prec):
+    """FP32-MFMA (and three-term BF16) refinement on the hard variant:
+    kappa * u_fp32 ~ 0.06 < 1, so refinement still contracts (slowly); the
+    refined X is compared with the long-double oracle against the same
+    kappa-based bound as FP64."""
     n = 48
     p = ti.laplace_tri((n, n, n), seed=3, bumps="every8", hard_sum=0.05)
     info = {}
     X = torch.empty_like(dev(p["B"]))
-    print("case hard mp fp32", flush=True)
+    print("case hard mp", prec, flush=True)
+    code = {"fp32": tt().TT_MP_FP32, "bf16": tt().TT_MP_BF16}[prec]
     try:
-        tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), X=X, prec=tt().TT_MP_FP32, tol=1e-13,
+        tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), X=X, prec=code, tol=1e-13,
                        max_iter=30, info=info)
     except tt().TTError as e:  # refinement may stall at the FP64 accuracy level
         assert e.code == tt().TT_ENOTCONV
@@ -86,6 +89,6 @@ def test_hard_variant_mixed_precision():
     Xld = oracle.lap_solve(p["T"], p["B"], precision="ld")
     kappa = cond1_estimate(p["T"], (n, n, n))
     e = rel(X.cpu().numpy(), Xld)
-    print(f"hard mp fp32: {info.get('iterations')} iterations, ratio {info.get('ratio'):.3e}, "
+    print(f"hard mp {prec}: {info.get('iterations')} iterations, ratio {info.get('ratio'):.3e}, "
           f"error {e:.3e}, kappa*u {kappa * U64:.3e}", flush=True)
     assert e <= 8 * kappa * U64

@@ -231,43 +231,72 @@ def test_directional_fd_cfg4_size():
 
 
 # ---------------------------------------------------------------- mixed precision (a6)
+MP = ["fp32", "bf16"]
+
+
+def mp(name):
+    return {"fp32": tt().TT_MP_FP32, "bf16": tt().TT_MP_BF16}[name]
+
+
+@pytest.mark.parametrize("prec", MP)
 @pytest.mark.parametrize("shape,seed", [((40, 40, 40), 1), ((96, 80, 72), 2)])
-def test_mixed_precision_general(shape, seed):
+def test_mixed_precision_general(shape, seed, prec):
     p = ti.laplace_dense(shape, seed=seed)
     info = {}
-    print("case mp general", shape, flush=True)
-    X = host(tt().solve_general(p["A"], dev(p["B"]), prec=tt().TT_MP_FP32, tol=1e-13, info=info))
+    print("case mp general", shape, prec, flush=True)
+    X = host(tt().solve_general(p["A"], dev(p["B"]), prec=mp(prec), tol=1e-13, info=info))
     Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
     assert rel(X, Xo) <= TOL
     # an FP32-accurate inner solve gains about 7 digits per step
     assert 1 <= info["iterations"] <= 4 and info["ratio"] <= 1e-13
 
 
-def test_mixed_precision_triangular():
+@pytest.mark.parametrize("prec", MP)
+def test_mixed_precision_triangular(prec):
     p = ti.laplace_tri((50, 61, 47), seed=3)
     info = {}
-    print("case mp tri", flush=True)
-    X = host(tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), prec=tt().TT_MP_FP32, info=info))
+    print("case mp tri", prec, flush=True)
+    X = host(tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), prec=mp(prec), info=info))
     assert rel(X, oracle.lap_solve(p["T"], p["B"])) <= TOL
     assert 1 <= info["iterations"] <= 4
 
 
-def test_mixed_precision_first_correction_is_fp32_sized():
-    """The low-precision solve really runs in FP32: the first correction is of
-    FP32 size relative to X, and one FP64 refinement step brings the error
-    far below it.  With max_iter = 1 and an unreachable tol the call reports
-    TT_ENOTCONV and leaves the refined X in place."""
-    p = ti.laplace_tri((64, 64, 64), seed=4)  # 4 leaf blocks per mode: FP32 updates occur
+def one_refinement_step(p, prec):
     info = {}
     X = torch.empty_like(dev(p["B"]))
-    print("case mp one step", flush=True)
     with pytest.raises(tt().TTError) as e:
-        tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), X=X, prec=tt().TT_MP_FP32, tol=1e-300,
-                       max_iter=1, info=info)
+        tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]), X=X, prec=prec, tol=1e-300, max_iter=1, info=info)
     assert e.value.code == tt().TT_ENOTCONV
     assert info["iterations"] == 1
-    assert 1e-11 < info["ratio"] < 1e-4
-    assert rel(host(X), oracle.lap_solve(p["T"], p["B"])) <= 1e-9
+    return host(X), info["ratio"]
+
+
+@pytest.mark.parametrize("prec", MP)
+def test_mixed_precision_first_correction_is_fp32_sized(prec):
+    """The low-precision solve really runs at FP32 accuracy: the first
+    correction is of FP32 size relative to X, and one FP64 refinement step
+    brings the error far below it.  With max_iter = 1 and an unreachable tol
+    the call reports TT_ENOTCONV and leaves the refined X in place."""
+    p = ti.laplace_tri((64, 64, 64), seed=4)  # 4 leaf blocks per mode: low-precision updates occur
+    print("case mp one step", prec, flush=True)
+    X, ratio = one_refinement_step(p, mp(prec))
+    assert 1e-11 < ratio < 1e-4
+    assert rel(X, oracle.lap_solve(p["T"], p["B"])) <= 1e-9
+
+
+def test_bf16_split_path_is_its_own():
+    """The BF16 solve takes its own arithmetic path (three-term BF16
+    products, not the FP32 MFMA and not FP64): after one refinement step its
+    X differs from the FP32 one, while both are FP32-accurate solves refined
+    once; and a single BF16 term could not reach that accuracy (u_bf16 =
+    2^-8 per product would leave a first correction near 1e-3)."""
+    p = ti.laplace_tri((64, 64, 64), seed=4)
+    print("case bf16 path", flush=True)
+    Xf, rf = one_refinement_step(p, tt().TT_MP_FP32)
+    Xb, rb = one_refinement_step(p, tt().TT_MP_BF16)
+    assert not np.array_equal(Xf, Xb)
+    assert rf != rb
+    assert rb < 1e-5
 
 
 def test_plan_coefficient_grads():

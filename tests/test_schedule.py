@@ -121,7 +121,7 @@ def test_workspace_bound_covers_every_pattern(shape, bumps):
         T = ti.laplace_tri(shape, seed=3, bumps=bumps)["T"]
     info = tt.schedule_info(T, shape)
     N = int(np.prod(shape))
-    for prec in (tt.TT_FP64, tt.TT_MP_FP32):
+    for prec in (tt.TT_FP64, tt.TT_MP_FP32, tt.TT_MP_BF16):
         bound = tt.workspace_bytes(shape, prec)
         assert bound >= info["plan_bytes"] + 8 * N, (bound, info["plan_bytes"])
     assert tt.workspace_bytes(shape, tt.TT_MP_FP32) >= tt.workspace_bytes(shape, tt.TT_FP64)
