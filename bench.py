@@ -137,7 +137,8 @@ class _Progress(dict):
 
 def extras(args):
     """The other workloads of the method, timed the same way (inputs resident
-    in HBM, HIP events on the caller's stream)."""
+    in HBM, HIP events on the caller's stream).  args.only: None (all) or a
+    list of name prefixes."""
     import torch
 
     import paper_1905_09539_amd as tt
@@ -145,52 +146,64 @@ def extras(args):
     out = _Progress()
     steps = max(2, args.steps // 4)
 
-    # dense coefficients, d = 3, n = 512 (Algorithm 1: transforms + solve)
-    n = 512
-    p = ti.laplace_dense((n, n, n), seed=args.seed)
-    B = torch.from_numpy(p["B"]).cuda()
-    X = torch.empty_like(B)
-    plan = tt.Plan(p["A"], B.shape, general=True)
-    ms = _timed(lambda: plan.solve(B, X), steps, 1)
-    plan.status()
-    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
-    out["dense_512"] = {"ms": ms, "tflops": plan.flops / (ms * 1e-3) / 1e12, "flops": plan.flops,
-                        "host_schur_s": plan.info()["schur_seconds"], "residual": _residual(Ad, X, B)}
-    del plan, B, X, Ad, p
-    torch.cuda.empty_cache()
+    def want(name):
+        return args.only is None or any(name.startswith(w) for w in args.only)
 
-    # mixed precision vs FP64, d = 3, n = 768, eigenvalue sums in [3, 6]
-    n = 768
-    p = ti.laplace_dense((n, n, n), seed=args.seed)
-    B = torch.from_numpy(p["B"]).cuda()
-    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
-    X64 = torch.empty_like(B)
-    Xmp = torch.empty_like(B)
-    plan64 = tt.Plan(p["A"], B.shape, general=True)
-    ms64 = _timed(lambda: plan64.solve(B, X64), 2, 1)
-    plan64.status()
-    r64 = _residual(Ad, X64, B)
-    del plan64
-    torch.cuda.empty_cache()
-    out["mixed_768"] = {"ms_fp64": ms64, "residual_fp64": r64}
-    for name, prec in (("fp32", tt.TT_MP_FP32), ("bf16", tt.TT_MP_BF16)):
-        planmp = tt.Plan(p["A"], B.shape, general=True, prec=prec, tol=1e-13)
-        msmp = _timed(lambda: planmp.solve(B, Xmp), 2, 1)
-        planmp.status()
-        info = planmp.info()
-        rmp = _residual(Ad, Xmp, B)
-        diff = float(torch.linalg.vector_norm(Xmp - X64) / torch.linalg.vector_norm(X64))
-        out["mixed_768"].update({f"ms_mp_{name}": msmp, f"speedup_{name}": ms64 / msmp,
-                                 f"iterations_{name}": info["iterations"], f"last_ratio_{name}": info["ratio"],
-                                 f"residual_mp_{name}": rmp, f"rel_diff_{name}_vs_fp64": diff})
-        del planmp
+    def flush():
+        torch.cuda.synchronize()
         torch.cuda.empty_cache()
-    out["mixed_768"] = out["mixed_768"]
-    del B, Ad, X64, Xmp, p
-    torch.cuda.empty_cache()
+
+    if want("dense_512"):
+        # dense coefficients, d = 3, n = 512 (Algorithm 1: transforms + solve)
+        n = 512
+        p = ti.laplace_dense((n, n, n), seed=args.seed)
+        B = torch.from_numpy(p["B"]).cuda()
+        X = torch.empty_like(B)
+        plan = tt.Plan(p["A"], B.shape, general=True)
+        ms = _timed(lambda: plan.solve(B, X), steps, 1)
+        plan.status()
+        Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+        out["dense_512"] = {"ms": ms, "tflops": plan.flops / (ms * 1e-3) / 1e12, "flops": plan.flops,
+                            "host_schur_s": plan.info()["schur_seconds"], "residual": _residual(Ad, X, B)}
+        del plan, B, X, Ad, p
+        flush()
+
+    if want("mixed_768"):
+        # mixed precision vs FP64, d = 3, n = 768, eigenvalue sums in [3, 6]
+        n = 768
+        p = ti.laplace_dense((n, n, n), seed=args.seed)
+        B = torch.from_numpy(p["B"]).cuda()
+        Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+        X64 = torch.empty_like(B)
+        Xmp = torch.empty_like(B)
+        plan64 = tt.Plan(p["A"], B.shape, general=True)
+        ms64 = _timed(lambda: plan64.solve(B, X64), 2, 1)
+        plan64.status()
+        r64 = _residual(Ad, X64, B)
+        del plan64
+        flush()
+        res = {"ms_fp64": ms64, "residual_fp64": r64}
+        for name, prec in (("fp32", tt.TT_MP_FP32), ("bf16", tt.TT_MP_BF16)):
+            planmp = tt.Plan(p["A"], B.shape, general=True, prec=prec, tol=1e-13)
+            msmp = _timed(lambda: planmp.solve(B, Xmp), 2, 1)
+            planmp.status()
+            info = planmp.info()
+            rmp = _residual(Ad, Xmp, B)
+            diff = float(torch.linalg.vector_norm(Xmp - X64) / torch.linalg.vector_norm(X64))
+            res.update({f"ms_mp_{name}": msmp, f"speedup_{name}": ms64 / msmp,
+                        f"iterations_{name}": info["iterations"], f"last_ratio_{name}": info["ratio"],
+                        f"residual_mp_{name}": rmp, f"rel_diff_{name}_vs_fp64": diff})
+            del planmp
+            flush()
+        out["mixed_768"] = res
+        del B, Ad, X64, Xmp, p
+        flush()
 
     # pair form, d = 4: (96, 96, 96, 96) and the merge case (1024, 1024, 8, 8)
     for shp in [(96, 96, 96, 96), (1024, 1024, 8, 8)]:
+        key = "pair_" + "x".join(str(x) for x in shp)
+        if not want(key):
+            continue
         p = ti.pair_tri(shp, seed=args.seed)
         A = [torch.from_numpy(a).cuda() for a in p["A"]]
         C = [torch.from_numpy(c).cuda() for c in p["C"]]
@@ -199,29 +212,33 @@ def extras(args):
         plan = tt.Plan(A, B.shape, C=C)
         ms = _timed(lambda: plan.solve(B, X), steps, 1)
         plan.status()
-        out["pair_" + "x".join(str(x) for x in shp)] = {"ms": ms, "flops": plan.flops,
-                                                         "tflops": plan.flops / (ms * 1e-3) / 1e12}
+        out[key] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12}
         del plan, A, C, B, X, p
-        torch.cuda.empty_cache()
+        flush()
 
-    # dense pairs, d = 4 (96, 96, 96, 96): host QZ per mode, then transforms
-    # and the triangular solve on the GPU
-    p = ti.pair_dense((96, 96, 96, 96), seed=args.seed)
-    B = torch.from_numpy(p["B"]).cuda()
-    X = torch.empty_like(B)
-    plan = tt.Plan(p["A"], B.shape, C=p["C"], general=True)
-    ms = _timed(lambda: plan.solve(B, X), steps, 1)
-    plan.status()
-    Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
-    Cd = [torch.from_numpy(c).cuda() for c in p["C"]]
-    out["general_pair_96x96x96x96"] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
-                                       "host_qz_s": plan.info()["schur_seconds"],
-                                       "residual": _pair_residual(Ad, Cd, X, B)}
-    del plan, Ad, Cd, B, X, p
-    torch.cuda.empty_cache()
+    if want("general_pair"):
+        # dense pairs, d = 4 (96, 96, 96, 96): host QZ per mode, then
+        # transforms and the triangular solve on the GPU
+        p = ti.pair_dense((96, 96, 96, 96), seed=args.seed)
+        B = torch.from_numpy(p["B"]).cuda()
+        X = torch.empty_like(B)
+        plan = tt.Plan(p["A"], B.shape, C=p["C"], general=True)
+        ms = _timed(lambda: plan.solve(B, X), steps, 1)
+        plan.status()
+        Ad = [torch.from_numpy(a).cuda() for a in p["A"]]
+        Cd = [torch.from_numpy(c).cuda() for c in p["C"]]
+        out["general_pair_96x96x96x96"] = {"ms": ms, "flops": plan.flops,
+                                           "tflops": plan.flops / (ms * 1e-3) / 1e12,
+                                           "host_qz_s": plan.info()["schur_seconds"],
+                                           "residual": _pair_residual(Ad, Cd, X, B)}
+        del plan, Ad, Cd, B, X, p
+        flush()
 
     # second operator class (eq. (3.1)), triangular, d = 3 and d = 4
     for shp in [(384, 384, 384), (96, 96, 96, 96)]:
+        key = "gsylv_" + "x".join(str(x) for x in shp)
+        if not want(key):
+            continue
         p = ti.gsylv_tri(shp, seed=args.seed)
         A = [torch.from_numpy(a).cuda() for a in p["A"]]
         C = torch.from_numpy(p["C"]).cuda()
@@ -230,58 +247,60 @@ def extras(args):
         plan = tt.Plan(A, B.shape, C=C, gsylv=True)
         ms = _timed(lambda: plan.solve(B, X), steps, 1)
         plan.status()
-        R = B - torch.movedim(torch.tensordot(A[0], X, dims=([1], [0])), 0, 0)
+        # ||B - X x_1 A_1 - X x_1 C x_2 A_2 .. x_d A_d||_F / ||B||_F
+        R = B - torch.tensordot(A[0], X, dims=([1], [0]))
         Y = X
         for nu in range(len(shp)):
             Y = torch.movedim(torch.tensordot(C if nu == 0 else A[nu], Y, dims=([1], [nu])), 0, nu)
         R -= Y
-        out["gsylv_" + "x".join(str(x) for x in shp)] = {
-            "ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
-            "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
+        out[key] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
+                    "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
         del plan, A, C, B, X, p, R, Y
-        torch.cuda.empty_cache()
+        flush()
 
-    # order 5 (Laplace-like, merged pair of modes), (40, 40, 40, 40, 40)
-    shp = (40, 40, 40, 40, 40)
-    p = ti.laplace_tri(shp, seed=args.seed)
-    T = [torch.from_numpy(t).cuda() for t in p["T"]]
-    B = torch.from_numpy(p["B"]).cuda()
-    X = torch.empty_like(B)
-    plan = tt.Plan(T, B.shape)
-    ms = _timed(lambda: plan.solve(B, X), steps, 1)
-    plan.status()
-    R = B.clone()
-    for mu in range(5):
-        R -= torch.movedim(torch.tensordot(T[mu], X, dims=([1], [mu])), 0, mu)
-    out["order5_40"] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
-                        "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
-    del plan, T, B, X, p, R
-    torch.cuda.empty_cache()
+    if want("order5"):
+        # order 5 (Laplace-like, merged pair of modes), (40, 40, 40, 40, 40)
+        shp = (40, 40, 40, 40, 40)
+        p = ti.laplace_tri(shp, seed=args.seed)
+        T = [torch.from_numpy(t).cuda() for t in p["T"]]
+        B = torch.from_numpy(p["B"]).cuda()
+        X = torch.empty_like(B)
+        plan = tt.Plan(T, B.shape)
+        ms = _timed(lambda: plan.solve(B, X), steps, 1)
+        plan.status()
+        R = B.clone()
+        for mu in range(5):
+            R -= torch.movedim(torch.tensordot(T[mu], X, dims=([1], [mu])), 0, mu)
+        out["order5_40"] = {"ms": ms, "flops": plan.flops, "tflops": plan.flops / (ms * 1e-3) / 1e12,
+                            "residual": float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))}
+        del plan, T, B, X, p, R
+        flush()
 
-    # adjoint: 64 uneven d = 3 problems, forward + backward (dB and dT)
-    probs = ti.uneven_batch(64, 32, 192, seed=args.seed)
-    T = [[torch.from_numpy(t).cuda() for t in q["T"]] for q in probs]
-    Bs = [torch.from_numpy(q["B"]).cuda() for q in probs]
-    Gs = [torch.from_numpy(q["G"]).cuda() for q in probs]
-    plan = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs])
-    Xs = [torch.empty_like(b) for b in Bs]
-    msf = _timed(lambda: plan.solve(Bs, Xs), steps, 1)
-    plan.status()
-    msb = _timed(lambda: tt.solve_backward_batched(T, Xs, Gs), steps, 1)
-    # the same backward with a reusable adjoint plan (planning and workspace
-    # allocation outside the timed region, as in a training loop)
-    planb = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs], trans=True)
-    dBs = [torch.empty_like(g) for g in Gs]
-    dTs = [[torch.empty_like(t) for t in Tb] for Tb in T]
+    if want("adjoint"):
+        # adjoint: 64 uneven d = 3 problems, forward + backward (dB and dT)
+        probs = ti.uneven_batch(64, 32, 192, seed=args.seed)
+        T = [[torch.from_numpy(t).cuda() for t in q["T"]] for q in probs]
+        Bs = [torch.from_numpy(q["B"]).cuda() for q in probs]
+        Gs = [torch.from_numpy(q["G"]).cuda() for q in probs]
+        plan = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs])
+        Xs = [torch.empty_like(b) for b in Bs]
+        msf = _timed(lambda: plan.solve(Bs, Xs), steps, 1)
+        plan.status()
+        msb = _timed(lambda: tt.solve_backward_batched(T, Xs, Gs), steps, 1)
+        # the same backward with a reusable adjoint plan (planning and
+        # workspace allocation outside the timed region, as in a training loop)
+        planb = tt.Plan(None, batch_T=T, batch_shapes=[q["B"].shape for q in probs], trans=True)
+        dBs = [torch.empty_like(g) for g in Gs]
+        dTs = [[torch.empty_like(t) for t in Tb] for Tb in T]
 
-    def backward():
-        planb.solve(Gs, dBs)
-        planb.coefficient_grads(T, Xs, dBs, dTs)
+        def backward():
+            planb.solve(Gs, dBs)
+            planb.coefficient_grads(T, Xs, dBs, dTs)
 
-    msbp = _timed(backward, steps, 1)
-    planb.status()
-    out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "ms_backward_plan": msbp,
-                              "forward_flops": plan.flops}
+        msbp = _timed(backward, steps, 1)
+        planb.status()
+        out["adjoint_batch64"] = {"ms_forward": msf, "ms_backward": msb, "ms_backward_plan": msbp,
+                                  "forward_flops": plan.flops}
     return dict(out)
 
 
@@ -296,6 +315,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cores", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only", type=lambda v: v.split(","), default=None,
+                    help="run only the other workloads whose names start with these comma-separated prefixes "
+                         "(no headline solve; prints one JSON object of their results)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step's kernels directly instead of replaying a recorded HIP graph")
     args = ap.parse_args()
@@ -309,6 +331,10 @@ def main():
 
     import paper_1905_09539_amd as tt
     import tt_inputs as ti
+
+    if args.only is not None:
+        print(json.dumps({"workloads": extras(args)}), flush=True)
+        return
 
     n = args.n
     p = ti.laplace_tri((n, n, n), seed=args.seed, bumps="every8")

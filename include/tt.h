@@ -66,7 +66,11 @@ typedef struct {
     int nmin;           /* leaf block edge per mode (the paper's n_min,
                            Algorithm 2); 0 = default (16 for d<=3, 8 for d=4) */
     int prec;           /* tt_prec                                           */
-    double tol;         /* refinement stop: ||D||_F / ||X||_F <= tol         */
+    double tol;         /* refinement stop: ||D||_F / ||X||_F <= tol, or
+                           from the second correction on, contraction
+                           rho = ratio_k / ratio_{k-1} < 1/2 with
+                           rho * ratio_k <= tol (the next correction, about
+                           the error left in X, would be below tol)        */
     int max_iter;       /* refinement iteration cap                          */
     int deterministic;  /* accepted for interface stability: every path is
                            bitwise reproducible run to run (each output is

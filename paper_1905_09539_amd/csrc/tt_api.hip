@@ -597,6 +597,11 @@ int run_pipeline(tt_plan_s* P, const double* B, double* X, int lp, hipStream_t s
 // Mixed precision with FP64 iterative refinement:
 //   X_0 = solve_lp(B);  repeat  R = B - sum_mu X x_mu A_mu  (FP64),
 //   D = solve_lp(R),  X += D  until ||D||_F / ||X||_F <= tol or max_iter.
+// The iteration contracts linearly: D_{k+1} ~ rho D_k with rho estimated as
+// ratio_k / ratio_{k-1}, and D_{k+1} is about the error left in X after the
+// k-th correction.  So from the second correction on it also stops when
+// rho < 1/2 and rho * ratio_k <= tol (that next correction would be below
+// tol), which saves the last low-precision solve and FP64 residual.
 int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
     const HostProblem& hp = P->sched.probs[0];
     P->last_info[0] = 0;
@@ -607,6 +612,7 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
     int rc = run_pipeline(P, B, X, lp, st);
     if (rc) return rc;
     const int nb = sumsq_blocks();
+    double prev = 0.0;
     for (int it = 1; it <= P->max_iter; ++it) {
         TT_HIP_CHECK(launch_copy(B, P->R, hp.N, st));
         for (int mu = 0; mu < hp.d_user; ++mu) {
@@ -630,6 +636,11 @@ int run_refined(tt_plan_s* P, const double* B, double* X, hipStream_t st) {
         P->last_info[1] = ratio;
         if (!std::isfinite(ratio)) return fail(TT_ESINGULAR, "refinement produced a non-finite correction");
         if (ratio <= P->tol) return TT_OK;
+        if (it >= 2 && prev > 0.0) {
+            const double rho = ratio / prev;
+            if (rho < 0.5 && rho * ratio <= P->tol) return TT_OK;
+        }
+        prev = ratio;
     }
     return fail(TT_ENOTCONV, "mixed-precision refinement did not reach the tolerance");
 }
@@ -876,9 +887,9 @@ size_t plan_bound_bytes(int d, const int64_t* n, int prec) {
     }
     grads = (double)al((size_t)grads);
     const double lap = plan_tables_bound(D, nn, (D >= 4) ? 8 : 16, N) + std::max(std::max(general, pair), grads);
-    // second class: leaf edge 8 / 4, partial products W_1 .. W_{D-2}, pre
+    // second class: leaf edge 8 / 5, partial products W_1 .. W_{D-2}, pre
     // and post matrices and one pipeline tensor
-    const double cls2 = plan_tables_bound(D, nn, (D >= 4) ? 4 : 8, N) + (double)(D - 2) * tensor + 2.0 * (double)mats +
+    const double cls2 = plan_tables_bound(D, nn, (D >= 4) ? 5 : 8, N) + (double)(D - 2) * tensor + 2.0 * (double)mats +
                         tensor;
     return (size_t)std::ceil(std::max(lap, cls2)) + 4096;
 }

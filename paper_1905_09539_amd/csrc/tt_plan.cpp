@@ -164,8 +164,9 @@ static int32_t shape_index(Schedule& s, std::map<std::array<int, kMaxD>, int32_t
 int build_schedule(Schedule& s, int nmin, std::string& err) {
     const int D = s.D;
     // default leaf edge: 16 (order 3) / 8 (order 4); the second class's
-    // leaves (one wave, products over the orthant) take 8 / 4
-    if (nmin <= 0) nmin = (s.cls == 1) ? ((D >= 4) ? 4 : 8) : ((D >= 4) ? 8 : 16);
+    // leaves (one wave per block of at most 1000 unknowns, D - 1 block
+    // tensors in LDS) take 8 / 5
+    if (nmin <= 0) nmin = (s.cls == 1) ? ((D >= 4) ? 5 : 8) : ((D >= 4) ? 8 : 16);
     if (nmin < 2) nmin = 2;
     if (nmin > 20) {
         err = "nmin must be at most 20";

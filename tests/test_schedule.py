@@ -125,10 +125,10 @@ def test_workspace_bound_covers_every_pattern(shape, bumps):
         bound = tt.workspace_bytes(shape, prec)
         assert bound >= info["plan_bytes"] + 8 * N, (bound, info["plan_bytes"])
     assert tt.workspace_bytes(shape, tt.TT_MP_FP32) >= tt.workspace_bytes(shape, tt.TT_FP64)
-    # the second class (same schedule at its default leaf edge 8 / 4): the
+    # the second class (same schedule at its default leaf edge 8 / 5): the
     # partial products W_1 .. W_{d-2} and one pipeline tensor besides
     if len(shape) >= 3:
-        info2 = tt.schedule_info(T, shape, nmin=4 if len(shape) == 4 else 8)
+        info2 = tt.schedule_info(T, shape, nmin=5 if len(shape) == 4 else 8)
         assert tt.workspace_bytes(shape) >= info2["plan_bytes"] + 8 * N * (len(shape) - 1)
 
 
