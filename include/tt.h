@@ -262,8 +262,9 @@ int solve_backward_batched(int count, const int* d, const int64_t* const* n,
  *     TT_ESINGULAR if that solve met a zero pivot or a non-finite value.
  *   tt_plan_flops  returns the method's flop count (one FMA = 2 flops):
  *     2 * sum_mu (n_mu (n_mu - 1) / 2 + bumps_mu) * N / n_mu for the
- *     Laplace-like form, plus 2 n_mu N per mode product of the pair form
- *     (d products) and of the dense-coefficient pipeline (2d products).
+ *     Laplace-like form, plus per mode product of a pipeline 2 n_mu N for
+ *     a dense matrix and (n_mu + 1) N for an upper triangular one (the
+ *     pair form's C_mu^{-1}, whose zero blocks the product skips).
  *   Batched and adjoint plans are FP64 only; tt_plan_create with
  *     opts->prec = TT_MP_FP32 or TT_MP_BF16 (Laplace-like form) refines
  *     in FP64.

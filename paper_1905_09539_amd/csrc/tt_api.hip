@@ -1,5 +1,6 @@
 // C ABI of the solver (declared in include/tt.h): argument validation, plan
 // construction (host) and the ordered launch sequence on one HIP stream.
+#include <algorithm>
 #include <chrono>
 #include <thread>
 #include <cmath>
@@ -111,6 +112,7 @@ struct tt_plan_s {
     // row-major n_mu x n_mu device matrix per user mode; W: one tensor of
     // workspace
     std::vector<double*> pre, post;
+    std::vector<const double*> upper;  // uploaded matrices that are upper triangular
     double* W = nullptr;
     double pipe_flops = 0;
     // coefficient gradients (allocated on first use): split-K Gram workspace,
@@ -276,7 +278,36 @@ int upload(tt_plan_s* P, const std::vector<V>& v, V** dst) {
 int upload_matrix(tt_plan_s* P, const std::vector<double>& m, double** out) {
     int rc = dev_alloc(P, sizeof(double) * m.size(), (void**)out, "coefficient matrix");
     if (rc) return rc;
+    // an upper triangular matrix (C^{-1} of the pair forms) lets the mode
+    // product skip its zero K chunks
+    const int64_t n = (int64_t)std::llround(std::sqrt((double)m.size()));
+    bool up = n * n == (int64_t)m.size();
+    for (int64_t i = 1; up && i < n; ++i)
+        for (int64_t j = 0; j < i; ++j)
+            if (m[(size_t)(i * n + j)] != 0.0) {
+                up = false;
+                break;
+            }
+    if (up) P->upper.push_back(*out);
     return to_device(P, *out, m.data(), sizeof(double) * m.size());
+}
+
+bool is_upper(const tt_plan_s* P, const double* M) {
+    return std::find(P->upper.begin(), P->upper.end(), M) != P->upper.end();
+}
+
+// flops of one pass of mode products (one FMA = 2 flops): 2 n N per dense
+// matrix, (n + 1) N per upper triangular one (n (n + 1) / 2 FMAs per fibre)
+double chain_flops(const tt_plan_s* P, const std::vector<double*>& mats) {
+    const HostProblem& hp = P->sched.probs[0];
+    const int lead = hp.D - hp.d_user;
+    double f = 0;
+    for (size_t mu = 0; mu < mats.size() && (int)mu < hp.d_user; ++mu) {
+        if (!mats[mu]) continue;
+        const double n = (double)hp.n[lead + (int)mu];
+        f += (is_upper(P, mats[mu]) ? n + 1.0 : 2.0 * n) * (double)hp.N;
+    }
+    return f;
 }
 
 int alloc_tensor(tt_plan_s* P, int64_t N, double** out) {
@@ -556,8 +587,8 @@ int apply_chain(tt_plan_s* P, const double* src, double* fin, double* other, con
         double* tgt = ((m - 1 - i) % 2 == 0) ? fin : other;
         int64_t L, nm, R;
         mode_view(hp, modes[(size_t)i], L, nm, R);
-        TT_HIP_CHECK(launch_modeprod(cur, tgt, nullptr, mats[(size_t)modes[(size_t)i]], L, (int)nm, (int)nm, R, 1.0,
-                                     0.0, lp, st));
+        const double* M = mats[(size_t)modes[(size_t)i]];
+        TT_HIP_CHECK(launch_modeprod(cur, tgt, nullptr, M, L, (int)nm, (int)nm, R, 1.0, 0.0, lp, st, is_upper(P, M)));
         cur = tgt;
     }
     return TT_OK;
@@ -710,13 +741,7 @@ int pipeline_plan(tt_plan_s* P, int d, const int64_t* n, const std::vector<std::
                 return rc;
     }
     if ((rc = alloc_tensor(P, hp.N, &P->W))) return rc;
-    double f = 0;
-    const int lead = hp.D - hp.d_user;
-    for (int mu = 0; mu < hp.d_user; ++mu) {
-        if (!pre[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
-        if (mu < (int)post.size() && !post[(size_t)mu].empty()) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
-    }
-    P->pipe_flops = P->sched.stats.flops + f;
+    P->pipe_flops = P->sched.stats.flops + chain_flops(P, P->pre) + chain_flops(P, P->post);
     return TT_OK;
 }
 
@@ -1055,12 +1080,6 @@ static int pair_reduce(int d, const int64_t* n, std::vector<std::vector<double>>
     return TT_OK;
 }
 
-static double pipeline_flops(const HostProblem& hp, int products) {
-    double f = 0;
-    const int lead = hp.D - hp.d_user;
-    for (int mu = 0; mu < hp.d_user; ++mu) f += 2.0 * (double)hp.n[lead + mu] * (double)hp.N;
-    return f * products;
-}
 
 // Order 5 with device coefficients: Laplace-like (C NULL) or pair form (C:
 // exact C^{-1} reduction per mode), then the merge of two modes
@@ -1147,7 +1166,7 @@ int tt_plan_create(tt_plan* out, int d, const int64_t* n, const double* const* T
     for (int mu = 0; mu < d; ++mu)
         if ((rc = upload_matrix(P.get(), Cinv[(size_t)mu], &P->pre[(size_t)mu]))) return rc;
     if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
-    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 1);
+    P->pipe_flops = P->sched.stats.flops + chain_flops(P.get(), P->pre);
     P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P.release();
     return TT_OK;
@@ -1238,7 +1257,7 @@ int tt_plan_create_general(tt_plan* out, int d, const int64_t* n, const double* 
     }
     if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
     if ((rc = setup_refinement(P.get(), A, opts))) return rc;
-    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 2);
+    P->pipe_flops = P->sched.stats.flops + chain_flops(P.get(), P->pre) + chain_flops(P.get(), P->post);
     P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P.release();
     return TT_OK;
@@ -1311,7 +1330,7 @@ int tt_plan_create_general_pair(tt_plan* out, int d, const int64_t* n, const dou
         if ((rc = upload_matrix(P.get(), Z[(size_t)mu], &P->post[(size_t)mu]))) return rc;
     }
     if ((rc = alloc_tensor(P.get(), hp.N, &P->W))) return rc;
-    P->pipe_flops = P->sched.stats.flops + pipeline_flops(hp, 2);
+    P->pipe_flops = P->sched.stats.flops + chain_flops(P.get(), P->pre) + chain_flops(P.get(), P->post);
     P->build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = P.release();
     return TT_OK;

@@ -99,7 +99,9 @@ __device__ inline int64_t xcd_tile(int64_t b, int64_t nblocks) {
 // ---------------------------------------------------------------------------
 // Mode product.  Y[l, i, r] = alpha * sum_j M[i, j] X[l, j, r] + beta * Z[l, i, r]
 // with M row-major nout x nin (ld = nin).  Z may equal Y (read before write);
-// Y must not overlap X.
+// Y must not overlap X.  upper: M is upper triangular (square), so a tile
+// of output rows i >= i0 starts its K loop at the chunk holding j = i0 (the
+// skipped chunks hold only zeros of M; the sums are unchanged).
 //   R > 1 : MFMA rows = i (M rows), columns = c = l R + r (X columns).
 //   R == 1: MFMA rows = l (X rows, contiguous along j), columns = i.
 // Grid: row tiles x column tiles, flattened, renumbered per XCD.
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
                                                              const double* Z,
                                                              const double* __restrict__ M, int64_t L,
                                                              int nin, int nout, int64_t R, double alpha,
-                                                             double beta) {
+                                                             double beta, int upper) {
     __shared__ double As[kDKC * kDRow];
     __shared__ double Bs[kDKC * kDRow];
     __shared__ int64_t colOff[kDT];
@@ -132,6 +134,8 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = typename MAcc<LP>::type{0, 0, 0, 0};
     const int nchunk = (K + kDKC - 1) / kDKC;
+    // first K chunk: output rows of M start at row0 (R > 1) or col0 (R == 1)
+    const int ch0 = upper ? (int)min<int64_t>((colpath ? row0 : col0) / kDKC, nchunk) : 0;
 
     if (colpath) {
         if (tid < kDT) {
@@ -164,8 +168,8 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
 #pragma unroll
             for (int i = 0; i < 4; ++i) rb[i] = (kv && bval[i]) ? X[boff[i] + roff] : 0.0;
         };
-        gload(0);
-        for (int ch = 0; ch < nchunk; ++ch) {
+        gload(ch0 * kDKC);
+        for (int ch = ch0; ch < nchunk; ++ch) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 4; ++i) As[(la_k + i) * kDRow + la_r] = ra[i];
@@ -211,8 +215,8 @@ __global__ __launch_bounds__(kDThreads) void modeprod_kernel(const double* __res
                 rb[i] = (mv && k < K) ? Mrow[k] : 0.0;
             }
         };
-        gload(0);
-        for (int ch = 0; ch < nchunk; ++ch) {
+        gload(ch0 * kDKC);
+        for (int ch = ch0; ch < nchunk; ++ch) {
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -428,7 +432,7 @@ static unsigned elem_grid(int64_t n) {
 }
 
 hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
-                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st) {
+                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st, bool upper) {
     if (L <= 0 || R <= 0 || nout <= 0) return hipSuccess;
     const int64_t rows = (R > 1) ? nout : L;
     const int64_t cols = (R > 1) ? L * R : nout;
@@ -436,13 +440,13 @@ hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const do
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     if (lp == 2)
         hipLaunchKernelGGL(modeprod_kernel<2>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
-                           nout, R, alpha, beta);
+                           nout, R, alpha, beta, upper && nin == nout ? 1 : 0);
     else if (lp == 1)
         hipLaunchKernelGGL(modeprod_kernel<1>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
-                           nout, R, alpha, beta);
+                           nout, R, alpha, beta, upper && nin == nout ? 1 : 0);
     else
         hipLaunchKernelGGL(modeprod_kernel<0>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
-                           nout, R, alpha, beta);
+                           nout, R, alpha, beta, upper && nin == nout ? 1 : 0);
     return hipGetLastError();
 }
 

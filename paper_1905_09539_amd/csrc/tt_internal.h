@@ -191,8 +191,10 @@ hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t st
 
 // Dense kernels (tt_dense.hip).  Tensor viewed as [L][n_mu][R] for mode mu.
 // Y = alpha (X x_mu M) + beta Z with M row-major nout x nin; Z may be Y.
+// upper: M is upper triangular (square), its zero K chunks are skipped
 hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
-                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st);
+                           int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st,
+                           bool upper = false);
 // Several Gram products in two launches (one split-K Gram pass over all jobs,
 // one reduce pass): job j owns workgroups [wg_first, wg_first + nt^2 nsplit)
 // and output elements [el_first, el_first + n^2).

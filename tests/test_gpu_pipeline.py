@@ -96,6 +96,36 @@ def test_pair_matches_reduced_oracle(shape, seed):
         assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(p["B"])
 
 
+def test_pair_ill_conditioned_C():
+    """C_mu with diagonals spread over [1e-6, 1] (condition ~5e5): the exact
+    C^{-1} reduction (formed on the host, applied by triangular mode
+    products, which skip the zero K chunks of C^{-1}) against the
+    long-double direct substitution on the pair operator (no C^{-1}); its
+    error stays within a small factor of the FP64 direct substitution's."""
+    shape = (24, 20, 18)
+    p = ti.pair_tri(shape, seed=21, c_lo=1e-6)
+    kappa = max(np.linalg.cond(c) for c in p["C"])
+    print(f"case pair ill-conditioned C (kappa(C_mu) <= {kappa:.2e})", flush=True)
+    X = host(tt().solve_tri([dev(a) for a in p["A"]], dev(p["B"]), C=[dev(c) for c in p["C"]]))
+    Xld = oracle.pair_solve(p["A"], p["C"], p["B"], method="direct", precision="ld")
+    Xd = oracle.pair_solve(p["A"], p["C"], p["B"], method="direct")
+    e, ed = rel(X, Xld), rel(Xd, Xld)
+    print(f"pair, ill-conditioned C: GPU error {e:.3e}, FP64 direct substitution {ed:.3e}", flush=True)
+    assert e <= 100 * ed + 1e-14
+
+
+def test_pair_plan_flops_count_triangular_transforms():
+    """The pair plan's flop count: the triangular solve of T' = C^{-1} A (same
+    pattern as A, so the oracle's count for A) plus (n_mu + 1) N per
+    triangular mode product B x_mu C_mu^{-1}."""
+    shape = (70, 33, 20)
+    p = ti.pair_tri(shape, seed=22)
+    plan = tt().Plan([dev(a) for a in p["A"]], shape, C=[dev(c) for c in p["C"]])
+    N = int(np.prod(shape))
+    want = oracle.flops_tri(p["A"], shape) + sum((n + 1) * N for n in shape)
+    assert plan.flops == want
+
+
 def test_pair_merge_case_corner():
     """(1024, 1024, 8, 8): with triangular pairs, the solution on the far
     corner box depends only on that box, so the corner is a smaller pair

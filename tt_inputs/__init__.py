@@ -141,11 +141,22 @@ def laplace_dense(shape, seed=0, bumps="every8", hard_sum=None):
     return p
 
 
-def pair_tri(shape, seed=0, bumps="every8"):
-    """Pair form  sum_mu X x_1 C_1 ... x_mu A_mu ... x_d C_d = B."""
+def pair_tri(shape, seed=0, bumps="every8", c_lo=None):
+    """Pair form  sum_mu X x_1 C_1 ... x_mu A_mu ... x_d C_d = B.
+    c_lo: if given, the diagonal of each C_mu is log-uniform in [c_lo, 1]
+    (strict upper part N(0,1)/sqrt(n) scaled by c_lo) instead of U[1, 2]:
+    ill-conditioned C_mu."""
     shape = tuple(int(x) for x in shape)
     A = [quasi_triangular(n, rng(seed, ROLE_T, mu), bumps) for mu, n in enumerate(shape)]
-    C = [upper_triangular(n, rng(seed, ROLE_C, mu)) for mu, n in enumerate(shape)]
+    if c_lo is None:
+        C = [upper_triangular(n, rng(seed, ROLE_C, mu)) for mu, n in enumerate(shape)]
+    else:
+        C = []
+        for mu, n in enumerate(shape):
+            g = rng(seed, ROLE_C, mu)
+            c = np.triu(g.standard_normal((n, n)) * (c_lo / np.sqrt(max(n, 1))), 1)
+            c[np.diag_indices(n)] = np.exp(g.uniform(np.log(c_lo), 0.0, n))
+            C.append(c)
     B = gaussian_tensor(shape, rng(seed, ROLE_B))
     return {"A": A, "C": C, "B": B}
 
