@@ -81,7 +81,7 @@ constexpr int kTupBits4 = 4;     // D = 4: tuple coordinates < 16
 struct LeafGeom {
     int cap;                     // prod bmax
     int tsum;                    // sum bmax^2
-    int tamax;                   // max bmax^2
+    int tamax;                   // doubles of one staged T_mu[B, B+1] (odd pitch)
     int maxtup;                  // largest tuple grid (entries)
     int maxcpl;                  // most coupled tuples (a 2x2 block in some mode) of a leaf
     int maxH;                    // most hyperplanes

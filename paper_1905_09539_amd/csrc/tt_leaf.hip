@@ -416,7 +416,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
     const int cap = ls[0] * sz[0];
 
     // LDS: Xs | Ts (diagonal blocks, row pitch sz + 4, zero padded) | union
-    // {adjacent T block; element records + coupled-tuple list} | per-mode
+    // {adjacent T blocks (one part per mode); element records + coupled-tuple list} | per-mode
     // bit tables | offsets
     double* Xs = lds;
     double* Ts[D];
@@ -525,93 +525,118 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
         tbits[mu] = tb;
     }
 
-    // ---- 3. contributions of the next block along each mode
-#pragma unroll
-    for (int mu = 0; mu < D; ++mu) {
-        const int nxm = nx[mu];
-        if (nxm == 0) continue;  // uniform over the workgroup
+    // ---- 3. contributions of the next block along each mode,
+    // T_mu[B, B+1] x_mu X[B+1]: T_mu[B, B+1] staged in LDS (mode mu's part
+    // of the union region, odd row pitch), one thread per fibre along mu
+    auto ta_of = [&](int mu) { return Ta + mu * geom.tamax; };
+    // row pitch: 17 with zeros past nx (one unmasked chunk of sixteen
+    // columns), else nx | 1
+    auto ta_pitch = [&](int mu) { return nx[mu] <= 16 ? 17 : (nx[mu] | 1); };
+    auto stage = [&](int mu) {
+        const int nxm = nx[mu], tpn = ta_pitch(mu), r1 = r0[mu] + sz[mu];
+        const int w = (nxm <= 16) ? 16 : nxm;
         const gdouble* T = to_global(P.T[mu]);
         const int64_t n = P.n[mu];
-        const int r1 = r0[mu] + sz[mu];
-        const int tpn = nxm | 1;  // odd row pitch of T_mu[B, B+1] in LDS
-        for (int e = tid; e < sz[mu] * nxm; e += NT) {
-            const int i = e / nxm, j = e - (e / nxm) * nxm;
-            Ta[i * tpn + j] = T[(int64_t)(r0[mu] + i) * n + r1 + j];
+        double* ta = ta_of(mu);
+        for (int e = tid; e < sz[mu] * w; e += NT) {
+            const int i = e / w, j = e - (e / w) * w;
+            ta[i * tpn + j] = (j < nxm) ? T[(int64_t)(r0[mu] + i) * n + r1 + j] : 0.0;
         }
-        // each lane starts its row loop at its own row: the fibres of
-        // consecutive lanes lie a power of two apart for some modes, and in
-        // step they would all update one LDS bank (with the odd pitch the T
-        // reads of different rows fall in different banks too)
-        const int rot = tid % sz[mu];
-        // one thread per fibre along mu
-        const int F = cap / sz[mu];
+    };
+    auto fibre_origin = [&](int mu, int f, int& eb, int64_t& gb) {
+        eb = 0;
+        gb = gbase;
+        int rem = f;
+#pragma unroll
+        for (int nu = D - 1; nu >= 0; --nu) {
+            if (nu == mu) continue;
+            const int q = qdiv(rem, rsz[nu]);
+            const int c = rem - q * sz[nu];
+            rem = q;
+            eb += c * ls[nu];
+            gb += (int64_t)c * gs[nu];
+        }
+    };
+    // the fibre of the next block, sixteen rows at a time in registers
+    // (clamped loads, zeroed past nx)
+    auto load16 = [&](int mu, int64_t gb, int jc, double (&xn)[16]) {
         const int64_t nstep = (int64_t)sz[mu] * gs[mu];  // from row r0+i to row r1+i
-        auto fibre_origin = [&](int f, int& eb, int64_t& gb) {
-            eb = 0;
-            gb = gbase;
-            int rem = f;
 #pragma unroll
-            for (int nu = D - 1; nu >= 0; --nu) {
-                if (nu == mu) continue;
-                const int q = qdiv(rem, rsz[nu]);
-                const int c = rem - q * sz[nu];
-                rem = q;
-                eb += c * ls[nu];
-                gb += (int64_t)c * gs[nu];
-            }
-        };
-        // the fibre of the next block, sixteen rows at a time in registers
-        // (clamped loads, zeroed past nxm)
-        auto load16 = [&](int64_t gb, int jc, double (&xn)[16]) {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const bool v = jc + j < nxm;
-                const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
-                xn[j] = v ? x : 0.0;
-            }
-        };
-        // one row of T_mu[B, B+1] per output element
-        auto apply16 = [&](int eb, int jc, const double (&xn)[16]) {
+        for (int j = 0; j < 16; ++j) {
+            const bool v = jc + j < nx[mu];
+            const double x = X[gb + nstep + (int64_t)(v ? jc + j : jc) * gs[mu]];
+            xn[j] = v ? x : 0.0;
+        }
+    };
+    // one row of T_mu[B, B+1] per output element; each lane starts its row
+    // loop at its own row: the fibres of consecutive lanes lie a power of two
+    // apart for some modes, and in step they would all update one LDS bank
+    // (with the odd pitch the T reads of different rows fall in different
+    // banks too)
+    auto apply16 = [&](int mu, int eb, int jc, const double (&xn)[16]) {
+        const int nxm = nx[mu], tpn = ta_pitch(mu), rot = tid % sz[mu];
+        const double* ta = ta_of(mu);
+        if (nxm <= 16) {  // uniform: zero padded, no masking
             for (int ii = 0; ii < sz[mu]; ++ii) {
                 const int i = (ii + rot < sz[mu]) ? ii + rot : ii + rot - sz[mu];
-                const double* ti = Ta + i * tpn + jc;
+                const double* ti = ta + i * tpn;
                 double a0 = 0.0, a1 = 0.0;
 #pragma unroll
                 for (int j = 0; j < 16; j += 2) {
-                    const double t0 = (jc + j < nxm) ? ti[(jc + j < nxm) ? j : 0] : 0.0;
-                    const double t1 = (jc + j + 1 < nxm) ? ti[(jc + j + 1 < nxm) ? j + 1 : 0] : 0.0;
-                    a0 = fma(t0, xn[j], a0);
-                    a1 = fma(t1, xn[j + 1], a1);
+                    a0 = fma(ti[j], xn[j], a0);
+                    a1 = fma(ti[j + 1], xn[j + 1], a1);
                 }
                 Xs[eb + i * ls[mu]] -= a0 + a1;
             }
-        };
-        // the common case, at most one fibre per thread and one chunk: its
-        // loads are issued before the barrier that publishes the T block
-        const bool one = F <= NT && nxm <= 16;  // uniform
-        double xp[16];
-        int ebp = 0;
-        if (one && tid < F) {
-            int64_t gb = 0;
-            fibre_origin(tid, ebp, gb);
-            load16(gb, 0, xp);
+            return;
         }
-        __syncthreads();
-        if (one) {
-            if (tid < F) apply16(ebp, 0, xp);
-        } else {
-            for (int f = tid; f < F; f += NT) {
-                int eb = 0;
+        for (int ii = 0; ii < sz[mu]; ++ii) {
+            const int i = (ii + rot < sz[mu]) ? ii + rot : ii + rot - sz[mu];
+            const double* ti = ta + i * tpn + jc;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; j += 2) {
+                const double t0 = (jc + j < nxm) ? ti[(jc + j < nxm) ? j : 0] : 0.0;
+                const double t1 = (jc + j + 1 < nxm) ? ti[(jc + j + 1 < nxm) ? j + 1 : 0] : 0.0;
+                a0 = fma(t0, xn[j], a0);
+                a1 = fma(t1, xn[j + 1], a1);
+            }
+            Xs[eb + i * ls[mu]] -= a0 + a1;
+        }
+    };
+    {
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+            if (nx[mu] == 0) continue;  // uniform over the workgroup
+            stage(mu);
+            const int F = cap / sz[mu];
+            // at most one fibre per thread and one chunk: its loads are
+            // issued before the barrier that publishes the T block
+            const bool one = F <= NT && nx[mu] <= 16;  // uniform
+            double xp[16];
+            int ebp = 0;
+            if (one && tid < F) {
                 int64_t gb = 0;
-                fibre_origin(f, eb, gb);
-                for (int jc = 0; jc < nxm; jc += 16) {
-                    double xn[16];
-                    load16(gb, jc, xn);
-                    apply16(eb, jc, xn);
+                fibre_origin(mu, tid, ebp, gb);
+                load16(mu, gb, 0, xp);
+            }
+            __syncthreads();
+            if (one) {
+                if (tid < F) apply16(mu, ebp, 0, xp);
+            } else {
+                for (int f = tid; f < F; f += NT) {
+                    int eb = 0;
+                    int64_t gb = 0;
+                    fibre_origin(mu, f, eb, gb);
+                    for (int jc = 0; jc < nx[mu]; jc += 16) {
+                        double xn[16];
+                        load16(mu, gb, jc, xn);
+                        apply16(mu, eb, jc, xn);
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     __syncthreads();  // tables of step 2 visible, Ta free
     uint64_t rowbits[D];
@@ -837,11 +862,12 @@ LeafGeom leaf_geometry(int D, const int* bmax, int maxtup, int maxcpl, int maxH)
     for (int mu = 0; mu < D; ++mu) {
         g.cap *= bmax[mu];
         g.tsum += bmax[mu] * (bmax[mu] + 4);
-        g.tamax = std::max(g.tamax, bmax[mu] * (bmax[mu] | 1));  // T_mu[B, B+1] at an odd pitch
+        // T_mu[B, B+1] at an odd pitch (17 for up to sixteen columns)
+        g.tamax = std::max(g.tamax, bmax[mu] * std::max(17, bmax[mu] | 1));
     }
     // union of the adjacent block (doubles) and the element records plus the
     // coupled-tuple list (u16 each)
-    g.uwords = std::max(g.tamax, ((g.cap + maxcpl) * 2 + 7) / 8);
+    g.uwords = std::max(D * g.tamax, ((g.cap + maxcpl) * 2 + 7) / 8);
     return g;
 }
 
