@@ -57,6 +57,31 @@ def test_hard_variant_vs_long_double(n):
     assert e_gpu <= 10 * e_o64 + 1e-15
 
 
+@pytest.mark.parametrize("n", [24, 48])
+def test_hard_coupled_tuples_vs_long_double(n):
+    """The smallest eigenvalue sum (0.05) reached by coupled tuples too: the
+    8-unknown tuple of the first 2x2 blocks of the three modes (eigenvalue
+    0.05 + i (0.2 + 0.3 - 0.5)) and 4-unknown tuples of two such blocks with
+    a pinned 1x1 entry.  Same bounds as the 1x1 case: kappa-based against the
+    long-double oracle, and within a small factor of the FP64 oracle, which
+    solves every tuple by Gaussian elimination with partial pivoting."""
+    shape = (n, n, n)
+    p = ti.laplace_tri(shape, seed=3, bumps="every8", hard_sum=0.05, hard_coupled=True)
+    print(f"case hard coupled n={n}", flush=True)
+    X = tt().solve_tri([dev(t) for t in p["T"]], dev(p["B"]))
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy()
+    Xld = oracle.lap_solve(p["T"], p["B"], precision="ld")
+    X64 = oracle.lap_solve(p["T"], p["B"])
+    kappa = cond1_estimate(p["T"], shape)
+    e_gpu, e_o64 = rel(Xg, Xld), rel(X64, Xld)
+    print(f"hard coupled n={n}: kappa_1 ~ {kappa:.3e}, GPU error {e_gpu:.3e}, FP64 oracle error {e_o64:.3e}",
+          flush=True)
+    assert kappa > 1e5
+    assert e_gpu <= 8 * kappa * U64
+    assert e_gpu <= 10 * e_o64 + 1e-15
+
+
 @pytest.mark.parametrize("n", [24, 96])
 def test_benign_variant_vs_long_double(n):
     p = ti.laplace_tri((n, n, n), seed=3, bumps="every8")

@@ -103,12 +103,18 @@ def gaussian_tensor(shape, g: np.random.Generator) -> np.ndarray:
 # Workload recipes.  Each returns a dict of numpy arrays.
 # ---------------------------------------------------------------------------
 
-def laplace_tri(shape, seed=0, bumps="every8", diag=(1.0, 2.0), hard_sum=None):
+def laplace_tri(shape, seed=0, bumps="every8", diag=(1.0, 2.0), hard_sum=None, hard_coupled=False):
     """Triangular Laplace-like problem  sum_mu X x_mu T_mu = B.
 
     hard_sum: if given, real parts are drawn from U[hard_sum/d, 2] and one 1x1
     diagonal entry per mode is pinned to hard_sum/d, so that the smallest
     eigenvalue sum is exactly hard_sum.
+    hard_coupled (with hard_sum): also the first 2x2 block of every mode gets
+    real part hard_sum/d and imaginary parts 0.2, 0.3, 0.5, 0.7 (modes 0..3),
+    so that coupled tuples reach the same smallest sum: the tuple of the
+    first blocks of modes 0, 1, 2 has the eigenvalue
+    hard_sum + i (0.2 + 0.3 - 0.5) = hard_sum, and the tuples of two such
+    blocks with the pinned 1x1 entries have hard_sum + i (b_mu - b_nu).
     """
     shape = tuple(int(x) for x in shape)
     d = len(shape)
@@ -127,6 +133,12 @@ def laplace_tri(shape, seed=0, bumps="every8", diag=(1.0, 2.0), hard_sum=None):
             free = np.flatnonzero(~in_bump)
             if len(free):
                 t[free[-1], free[-1]] = hard_sum / d
+            if hard_coupled:
+                first = [i for i in range(n - 1) if t[i + 1, i] != 0.0]
+                if first:
+                    i, b = first[0], (0.2, 0.3, 0.5, 0.7)[mu]
+                    t[i, i] = t[i + 1, i + 1] = hard_sum / d
+                    t[i, i + 1], t[i + 1, i] = b, -b
         T.append(t)
     B = gaussian_tensor(shape, rng(seed, ROLE_B))
     return {"T": T, "B": B}
