@@ -38,12 +38,13 @@
 //   2. tuples hyperplane by hyperplane: 1x1 tuples one per thread in
 //      registers; coupled tuples are queued; after a barrier their sums
 //      past the tuple are formed one per thread, then each tuple of 2 or 4
-//      unknowns is solved by one thread in registers, larger ones in LDS
-//      (Gaussian elimination with partial pivoting throughout);
+//      unknowns is solved by one thread in registers, larger ones by sixteen
+//      lanes together (Gaussian elimination with partial pivoting
+//      throughout);
 //   3. X stored, W_k += Z_k.
 // LDS: X and Z_1 .. Z_{D-2} of the block (Z_1 holds the K chain in step 1),
 // the diagonal blocks, and a union of the staged off-diagonal block with the
-// coupled-tuple scratch.
+// sums past the coupled tuples.
 #include "tt_internal.h"
 
 #include <algorithm>
@@ -60,12 +61,8 @@ static_assert(kFib >= kMaxLeaf, "fibre registers must hold a leaf block edge");
 
 template <int D>
 struct L2Tup {
-    static constexpr int NE = 1 << D;  // unknowns of the largest tuple
-    static constexpr int CH = 32;      // coupled tuples of <= 4 unknowns per round
+    static constexpr int CH = 32;            // coupled tuples of <= 4 unknowns per round
     static constexpr int sbuf = CH * 4 * D;  // their sums past the tuple
-    static constexpr int slots = 2;    // tuples of 8 or 16 unknowns solved at once
-    // M (NE x NE), r, S_1 .. S_{D-1}, q, q'
-    static constexpr int slot = NE * NE + NE + (D - 1) * NE + 2 * NE;
 };
 
 // LDS carving (doubles) for the largest block of a launch.
@@ -104,8 +101,7 @@ L2Geom l2_geometry(int D, const int* bmax) {
     g.oZ = g.cap;
     g.oTd = g.oZ + (D - 2) * g.cap;
     g.oU = g.oTd + D * g.bm * g.tp;
-    const int pool = (D == 4) ? L2Tup<4>::sbuf + L2Tup<4>::slots * L2Tup<4>::slot
-                              : L2Tup<3>::sbuf + L2Tup<3>::slots * L2Tup<3>::slot;
+    const int pool = (D == 4) ? L2Tup<4>::sbuf : L2Tup<3>::sbuf;
     g.oList = g.oU + std::max(g.bm * g.top, pool);
     g.maxhyp = max_hyperplane(D, bmax);
     // coupled-tuple queue (u32) and three counters, in doubles
@@ -117,46 +113,6 @@ L2Geom l2_geometry(int D, const int* bmax) {
 // (e + 0.5) / s lies at least 0.5 / s from an integer, while the float
 // product is off by at most 2^-23 * 2^16 / s = 2^-7 / s.
 __device__ inline int qdiv2(int e, float rs) { return (int)(((float)e + 0.5f) * rs); }
-
-// Gaussian elimination with partial pivoting on an s x s system in LDS
-// (row-major M, right-hand side r, solution in r); false on a zero pivot or
-// a non-finite result.
-__device__ inline bool lds_gepp(int s, double* M, double* r) {
-    bool ok = true;
-    for (int k = 0; k < s; ++k) {
-        int piv = k;
-        double best = fabs(M[k * s + k]);
-        for (int i = k + 1; i < s; ++i)
-            if (fabs(M[i * s + k]) > best) {
-                best = fabs(M[i * s + k]);
-                piv = i;
-            }
-        if (best == 0.0) ok = false;
-        if (piv != k) {
-            for (int j = 0; j < s; ++j) {
-                const double t = M[k * s + j];
-                M[k * s + j] = M[piv * s + j];
-                M[piv * s + j] = t;
-            }
-            const double t = r[k];
-            r[k] = r[piv];
-            r[piv] = t;
-        }
-        const double rp = 1.0 / M[k * s + k];
-        for (int i = k + 1; i < s; ++i) {
-            const double f = M[i * s + k] * rp;
-            for (int j = k + 1; j < s; ++j) M[i * s + j] = fma(-f, M[k * s + j], M[i * s + j]);
-            r[i] = fma(-f, r[k], r[i]);
-        }
-    }
-    for (int k = s - 1; k >= 0; --k) {
-        double acc = r[k];
-        for (int j = k + 1; j < s; ++j) acc = fma(-M[k * s + j], r[j], acc);
-        r[k] = acc / M[k * s + k];
-        if (!isfinite(r[k])) ok = false;
-    }
-    return ok;
-}
 
 // Gaussian elimination with partial pivoting on a 4 x 4 system in registers
 // (all indices static); false on a zero pivot or a non-finite result.
@@ -424,15 +380,13 @@ __global__ __launch_bounds__(NT) void leaf2_kernel(const LeafDesc* __restrict__ 
         return ldot(row, src + e, c, from, sz[mu], ls[mu]);
     };
 
-    // coupled tuple (ne > 1) with LDS scratch sc
-    auto coupled = [&](const int (&a)[D], const int (&w)[D], int ne, double* sc) {
-        double* M = sc;
-        double* r = M + ne * ne;
-        double* S = r + ne;  // S_k at S + (k - 1) ne, k = 1 .. D-1
-        double* q = S + (D - 1) * ne;
-        double* q2 = q + ne;
-        // bit of each width-2 mode in the local unknown index (the last such
-        // mode owns bit 0)
+    // coupled tuple of 8 or 16 unknowns, sixteen lanes together (lane u of
+    // the group owns unknown u and row u of the tuple's system; rows past ne
+    // are identity rows): sums past the tuple per lane, the q chain through
+    // lane shuffles, Gaussian elimination with partial pivoting across the
+    // lanes (pivot search by a butterfly, row exchange and the pivot row by
+    // shuffles), back-substitution, then X and the Z chain
+    auto coupled16 = [&](const int (&a)[D], const int (&w)[D], int ne, int u) {
         int bit[D];
         {
             int b = 0;
@@ -442,69 +396,98 @@ __global__ __launch_bounds__(NT) void leaf2_kernel(const LeafDesc* __restrict__ 
                 if (w[mu] == 2) ++b;
             }
         }
-        auto coord = [&](int u, int mu) { return a[mu] + ((bit[mu] >= 0) ? ((u >> bit[mu]) & 1) : 0); };
-        auto elem = [&](int u) {
-            int e = 0;
+        auto coord = [&](int v, int mu) { return a[mu] + ((bit[mu] >= 0) ? ((v >> bit[mu]) & 1) : 0); };
+        const bool act = u < ne;
+        int cu[D], e = 0;
 #pragma unroll
-            for (int mu = 0; mu < D; ++mu) e += coord(u, mu) * ls[mu];
-            return e;
+        for (int mu = 0; mu < D; ++mu) {
+            cu[mu] = coord(u, mu);
+            e += cu[mu] * ls[mu];
+        }
+        double S[D];
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) S[mu] = act ? past(mu, cu[mu], a[mu] + w[mu], e) : 0.0;
+        double r = act ? Xs[e] - S[0] : 0.0;
+        // partner of u along mode k (itself for a 1x1 mode)
+        auto partner = [&](int k) { return (bit[k] >= 0) ? (u ^ (1 << bit[k])) : u; };
+        // one step of the chain: A_k,tuple applied to v (held one per lane) plus add
+        auto chain = [&](int k, double v, double add) {
+            const int pu = partner(k);
+            const double vp = __shfl(v, pu, 16);
+            double s = fma(tdiag(k, cu[k], cu[k]), v, add);
+            if (bit[k] >= 0) s = fma(tdiag(k, cu[k], coord(pu, k)), vp, s);
+            return act ? s : 0.0;
         };
-        for (int u = 0; u < ne; ++u) {
-            const int e = elem(u);
-            r[u] = Xs[e] - past(0, coord(u, 0), a[0] + w[0], e);
+        double q = S[1];
 #pragma unroll
-            for (int k = 1; k < D; ++k) S[(k - 1) * ne + u] = past(k, coord(u, k), a[k] + w[k], e);
-        }
-        // q_1 = S_1, q_k = A_k,tuple q_{k-1} + S_k
-        for (int u = 0; u < ne; ++u) q[u] = S[u];
+        for (int k = 2; k < D; ++k) q = chain(k, q, S[k]);
+        r -= q;
+        // row u of M = T_0,tuple (x) I + I (x) (A_1 (x) .. (x) A_{D-1})_tuple
+        double Mr[16];
 #pragma unroll
-        for (int k = 2; k < D; ++k) {
-            for (int u = 0; u < ne; ++u) {
-                const int cu = coord(u, k);
-                double s = fma(tdiag(k, cu, cu), q[u], S[(k - 1) * ne + u]);
-                if (bit[k] >= 0) {
-                    const int v = u ^ (1 << bit[k]);
-                    s = fma(tdiag(k, cu, coord(v, k)), q[v], s);
-                }
-                q2[u] = s;
-            }
-            for (int u = 0; u < ne; ++u) q[u] = q2[u];
-        }
-        // M = T_0,tuple (x) I + I (x) (A_1 (x) .. (x) A_{D-1})_tuple
-        for (int u = 0; u < ne; ++u) {
-            r[u] -= q[u];
-            for (int v = 0; v < ne; ++v) {
-                bool rest = true;  // u, v agree in modes >= 1
+        for (int v = 0; v < 16; ++v) {
+            double m = (u == v) ? 1.0 : 0.0;
+            if (act && v < ne) {
+                bool rest = true;
 #pragma unroll
-                for (int k = 1; k < D; ++k) rest = rest && coord(u, k) == coord(v, k);
-                double m = rest ? tdiag(0, coord(u, 0), coord(v, 0)) : 0.0;
-                if (coord(u, 0) == coord(v, 0)) {
+                for (int k = 1; k < D; ++k) rest = rest && cu[k] == coord(v, k);
+                m = rest ? tdiag(0, cu[0], coord(v, 0)) : 0.0;
+                if (cu[0] == coord(v, 0)) {
                     double pr = 1.0;
 #pragma unroll
-                    for (int k = 1; k < D; ++k) pr *= tdiag(k, coord(u, k), coord(v, k));
+                    for (int k = 1; k < D; ++k) pr *= tdiag(k, cu[k], coord(v, k));
                     m += pr;
                 }
-                M[u * ne + v] = m;
             }
+            Mr[v] = m;
         }
-        const bool good = lds_gepp(ne, M, r);
-        // X, then Z_k = A_k,tuple Z_{k-1} + S_k for k = 1 .. D-2 (Z_0 = x)
-        for (int u = 0; u < ne; ++u) Xs[elem(u)] = r[u];
-        const double* prev = r;
+        bool good = true;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            // pivot: the largest |M[i][k]| over rows i >= k (ties: lower row)
+            double key = (u >= k) ? fabs(Mr[k]) : -1.0;
+            int idx = u;
+#pragma unroll
+            for (int m = 8; m >= 1; m >>= 1) {
+                const double ok2 = __shfl_xor(key, m, 16);
+                const int oi = __shfl_xor(idx, m, 16);
+                if (ok2 > key || (ok2 == key && oi < idx)) {
+                    key = ok2;
+                    idx = oi;
+                }
+            }
+            if (!(key > 0.0)) good = false;
+            const int pv = idx;
+            // exchange rows k and pv
+            const int src = (u == k) ? pv : ((u == pv) ? k : u);
+#pragma unroll
+            for (int j = k; j < 16; ++j) Mr[j] = __shfl(Mr[j], src, 16);
+            r = __shfl(r, src, 16);
+            // eliminate below the pivot with row k
+            const double pk = __shfl(Mr[k], k, 16), rk = __shfl(r, k, 16);
+            const double f = (u > k) ? Mr[k] / pk : 0.0;
+#pragma unroll
+            for (int j = k + 1; j < 16; ++j) Mr[j] = fma(-f, __shfl(Mr[j], k, 16), Mr[j]);
+            r = fma(-f, rk, r);
+        }
+        // back-substitution: x_k from lane k, broadcast to the group
+        double x = 0.0, xs[16];
+#pragma unroll
+        for (int k = 15; k >= 0; --k) {
+            double acc = r;
+#pragma unroll
+            for (int j = k + 1; j < 16; ++j) acc = fma(-Mr[j], xs[j], acc);
+            const double xk = acc / Mr[k];
+            xs[k] = __shfl(xk, k, 16);
+            if (u == k) x = xk;
+        }
+        if (act && !isfinite(x)) good = false;
+        if (act) Xs[e] = x;
+        double z = x;
 #pragma unroll
         for (int k = 1; k <= D - 2; ++k) {
-            double* cur = (k & 1) ? q : q2;
-            for (int u = 0; u < ne; ++u) {
-                const int cu = coord(u, k);
-                double s = fma(tdiag(k, cu, cu), prev[u], S[(k - 1) * ne + u]);
-                if (bit[k] >= 0) {
-                    const int v = u ^ (1 << bit[k]);
-                    s = fma(tdiag(k, cu, coord(v, k)), prev[v], s);
-                }
-                cur[u] = s;
-            }
-            for (int u = 0; u < ne; ++u) Zs[(k - 1) * cap + elem(u)] = cur[u];
-            prev = cur;
+            z = chain(k, z, S[k]);
+            if (act) Zs[(k - 1) * cap + e] = z;
         }
         return good;
     };
@@ -669,15 +652,17 @@ __global__ __launch_bounds__(NT) void leaf2_kernel(const LeafDesc* __restrict__ 
                 }
                 __syncthreads();
             }
-            // tuples of 8 or 16 unknowns (2x2 blocks in three or more modes)
-            if (tid < Tup::slots) {
-                double* sc = U + Tup::sbuf + tid * Tup::slot;
+            // tuples of 8 or 16 unknowns (2x2 blocks in three or more modes):
+            // sixteen lanes per tuple, the groups of the workgroup in turn
+            {
+                constexpr int G = NT / 16;
+                const int grp = tid / 16, u = tid % 16;
                 int j = 0;
                 for (int k = 0; k < nc; ++k) {
                     int a[D], w[D];
                     const int ne = decode(qlist[k], a, w);
                     if (ne <= 4) continue;
-                    if (j++ % Tup::slots == tid && !coupled(a, w, ne, sc)) ok = false;
+                    if (j++ % G == grp && !coupled16(a, w, ne, u)) ok = false;  // uniform in the group
                 }
             }
             __syncthreads();
