@@ -224,7 +224,7 @@ int solve_backward(int d, const int64_t* n, const double* const* T,
  *   (A_1, C), host real Schur of A_2 .. A_d, the transforms on the GPU.
  *   A_host[mu], C_host: HOST row-major matrices.
  * B, X: device tensors as for solve_tri_tensor; X may alias B.  FP64 only
- * (opts->prec must be TT_FP64).  opts->nmin = 0 takes 8 (d = 3) / 4 (d = 4).
+ * (opts->prec must be TT_FP64).  opts->nmin = 0 takes 8 (d = 3) / 5 (d = 4).
  * Errors: TT_EINVAL (arguments, structure, C not upper triangular or with a
  * zero diagonal entry, no QZ / QR convergence), TT_ESINGULAR (zero pivot or
  * non-finite value: the uniqueness condition fails), TT_ENOMEM, TT_EHIP.
