@@ -117,6 +117,38 @@ def test_gsylv_128_residual_and_corner():
     assert e <= TOL
 
 
+def test_gsylv_96x4_residual_and_corner():
+    """The d = 4 benchmark workload (96^4, leaf edge 5): residual of the whole
+    solve (torch) and the self-contained far corner [76, 96)^4 against the
+    oracle's direct solve."""
+    shape = (96, 96, 96, 96)
+    p = ti.gsylv_tri(shape, seed=17, bumps="every8")
+    A = [dev(a) for a in p["A"]]
+    C = dev(p["C"])
+    B = dev(p["B"])
+    print("case gsylv 96^4", flush=True)
+    X = tt().solve_gsylv(A, C, B)
+    torch.cuda.synchronize()
+    R = B - torch.tensordot(A[0], X, dims=([1], [0]))
+    Z = X
+    for nu in range(4):
+        Z = torch.movedim(torch.tensordot(C if nu == 0 else A[nu], Z, dims=([1], [nu])), 0, nu)
+    R -= Z
+    r = float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
+    print(f"gsylv 96^4 residual {r:.3e}", flush=True)
+    assert r <= 1e-13
+    lo = [76] * 4
+    for mu in range(4):
+        while lo[mu] > 0 and p["A"][mu][lo[mu], lo[mu] - 1] != 0.0:
+            lo[mu] -= 1
+    sl = tuple(slice(l, None) for l in lo)
+    Xo = oracle.gsylv_solve([np.ascontiguousarray(a[l:, l:]) for a, l in zip(p["A"], lo)],
+                            np.ascontiguousarray(p["C"][lo[0]:, lo[0]:]), np.ascontiguousarray(p["B"][sl]))
+    e = rel(X.cpu().numpy()[sl], Xo)
+    print(f"gsylv 96^4 corner: {e:.3e}", flush=True)
+    assert e <= TOL
+
+
 def test_gsylv_shifted_kronecker():
     """Eq. (1.6): A_1 = -lambda I, operator A_d (x) .. (x) A_2 (x) C - lambda I."""
     shape = (18, 15, 12)

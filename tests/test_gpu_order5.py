@@ -82,3 +82,32 @@ def test_order5_plan_reuse_in_place_and_empty():
     q = ti.laplace_tri(z, seed=10, bumps="none")
     X = tt().solve_tri([dev(t) for t in q["T"]], dev(q["B"]))
     assert X.numel() == 0
+
+
+def test_order5_40_residual_and_corner():
+    """The order-5 benchmark workload (40^5, modes 3 and 4 merged into 1600):
+    residual of the whole solve (torch) and the self-contained far corner
+    [30, 40)^5 against the oracle's order-5 substitution."""
+    shape = (40, 40, 40, 40, 40)
+    p = ti.laplace_tri(shape, seed=8, bumps="every8")
+    T = [dev(t) for t in p["T"]]
+    B = dev(p["B"])
+    print("case order5 40^5", flush=True)
+    X = tt().solve_tri(T, B)
+    torch.cuda.synchronize()
+    R = B.clone()
+    for mu in range(5):
+        R -= torch.movedim(torch.tensordot(T[mu], X, dims=([1], [mu])), 0, mu)
+    r = float(torch.linalg.vector_norm(R) / torch.linalg.vector_norm(B))
+    print(f"order5 40^5 residual {r:.3e}", flush=True)
+    assert r <= 1e-13
+    lo = [30] * 5
+    for mu in range(5):
+        while lo[mu] > 0 and p["T"][mu][lo[mu], lo[mu] - 1] != 0.0:
+            lo[mu] -= 1
+    sl = tuple(slice(l, None) for l in lo)
+    Xo = oracle.lap_solve([np.ascontiguousarray(t[l:, l:]) for t, l in zip(p["T"], lo)],
+                          np.ascontiguousarray(p["B"][sl]))
+    e = rel(X.cpu().numpy()[sl], Xo)
+    print(f"order5 40^5 corner: {e:.3e}", flush=True)
+    assert e <= TOL
