@@ -238,6 +238,22 @@ def solve_general(A, B, X=None, nmin=0, prec=TT_FP64, tol=1e-13, max_iter=10, st
     return X
 
 
+# the dense-coefficient solve under its short name
+solve = solve_general
+
+
+def refine(A, B, X=None, prec=TT_MP_FP32, tol=1e-13, max_iter=10, dense=True, stream=None):
+    """Mixed-precision solve with FP64 iterative refinement (solve_general, or
+    solve_tri with dense=False and device triangular A); returns X and a dict
+    with the refinement iterations and the last correction ratio."""
+    info = {}
+    if dense:
+        X = solve_general(A, B, X=X, prec=prec, tol=tol, max_iter=max_iter, stream=stream, info=info)
+    else:
+        X = solve_tri(A, B, X=X, prec=prec, tol=tol, max_iter=max_iter, stream=stream, info=info)
+    return X, info
+
+
 def solve_backward(T, X, G, dB=None, grads=True, dense_grad=False, nmin=0, stream=None, workspace=None):
     """Adjoint of solve_tri for L with dL/dX = G: returns (dB, dT) with
     dB = Lam solving sum_mu Lam x_mu T_mu^T = G and dT[mu] = -Lam_(mu) X_(mu)^T

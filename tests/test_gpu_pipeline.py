@@ -292,6 +292,21 @@ def test_mixed_precision_triangular(prec):
     assert 1 <= info["iterations"] <= 4
 
 
+def test_refine_and_solve_names():
+    """tt.refine (mixed precision with FP64 refinement, dense or triangular
+    coefficients) and tt.solve (the dense-coefficient solve) against the
+    oracle."""
+    p = ti.laplace_dense((30, 26, 22), seed=9)
+    print("case refine / solve", flush=True)
+    Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
+    X, info = tt().refine(p["A"], dev(p["B"]), prec=tt().TT_MP_BF16)
+    assert rel(host(X), Xo) <= TOL and 1 <= info["iterations"] <= 3
+    assert rel(host(tt().solve(p["A"], dev(p["B"]))), Xo) <= TOL
+    q = ti.laplace_tri((30, 26, 22), seed=9)
+    X, info = tt().refine([dev(t) for t in q["T"]], dev(q["B"]), dense=False)
+    assert rel(host(X), oracle.lap_solve(q["T"], q["B"])) <= TOL
+
+
 def one_refinement_step(p, prec):
     info = {}
     X = torch.empty_like(dev(p["B"]))
