@@ -422,6 +422,136 @@ __global__ void f32_to_f64_kernel(const float* __restrict__ x, double* __restric
 }
 
 // ---------------------------------------------------------------------------
+// The same mode product on 128x128 tiles (FP64): four waves of 64x64, each
+// 4x4 MFMA 16x16x4 blocks, so every K chunk staged through LDS feeds four
+// times the MFMA work of the 64x64 tile for the same two barriers, and each
+// operand element read from memory serves twice as many products.  Used for
+// large products (the dense transforms and the refinement residuals).
+// ---------------------------------------------------------------------------
+constexpr int kBT = 128;    // tile edge
+constexpr int kBRow = 144;  // LDS row pitch (doubles): the two K rows a half-wave reads fall in disjoint bank halves
+
+__global__ __launch_bounds__(kDThreads) __attribute__((amdgpu_waves_per_eu(2))) void modeprod128_kernel(const double* __restrict__ X, double* Y,
+                                                                const double* Z, const double* __restrict__ M,
+                                                                int64_t L, int nin, int nout, int64_t R,
+                                                                double alpha, double beta, int upper) {
+    __shared__ double As[kDKC * kBRow];
+    __shared__ double Bs[kDKC * kBRow];
+    __shared__ int64_t colOff[kBT];
+    const int tid = threadIdx.x;
+    const bool colpath = R > 1;
+    const int64_t rows = colpath ? nout : L;
+    const int64_t cols = colpath ? L * R : nout;
+    const int64_t nrt = (rows + kBT - 1) / kBT;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t row0 = (t % nrt) * kBT;
+    const int64_t col0 = (t / nrt) * kBT;
+    const int K = nin;
+    const int nchunk = (K + kDKC - 1) / kDKC;
+    const int ch0 = upper ? (int)min<int64_t>((colpath ? row0 : col0) / kDKC, nchunk) : 0;
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const int li = lane & 15, lk = lane >> 4;
+    MAcc<0>::type acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = MAcc<0>::type{0.0, 0.0, 0.0, 0.0};
+
+    // loaders: A rows (contiguous along K) as 128 rows x 16: row tid / 2,
+    // eight consecutive K from (tid % 2) * 8; B as 16 x 128 (colpath: one
+    // column per lane, K rows 8 * (tid / 128) ..; rowpath: like A)
+    const int ar = tid >> 1, ak = (tid & 1) * 8;
+    const int bc = tid & 127, bk = (tid >> 7) * 8;
+    double ra[8], rb[8];
+    const bool aval = colpath ? (row0 + ar) < rows : (row0 + ar) < rows;
+    const double* Arow = colpath ? M + (row0 + ar) * (int64_t)nin : X + (row0 + ar) * (int64_t)nin;
+    const bool bval = colpath ? (col0 + bc) < cols : (col0 + ar) < cols;
+    const double* Brow = colpath ? nullptr : M + (col0 + ar) * (int64_t)nin;
+    if (colpath && tid < kBT) {
+        const int64_t c = col0 + tid;
+        const int64_t l = c / R, r = c - (c / R) * R;
+        colOff[tid] = (c < cols) ? l * (int64_t)nin * R + r : 0;
+    }
+    __syncthreads();
+    const int64_t boff = colpath ? colOff[bc] : 0;
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = kc + ak + i;
+            ra[i] = (aval && k < K) ? Arow[k] : 0.0;
+        }
+        if (colpath) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = kc + bk + i;
+                rb[i] = (bval && k < K) ? X[boff + (int64_t)k * R] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = kc + ak + i;
+                rb[i] = (bval && k < K) ? Brow[k] : 0.0;
+            }
+        }
+    };
+    gload(ch0 * kDKC);
+    for (int ch = ch0; ch < nchunk; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As[(ak + i) * kBRow + ar] = ra[i];
+        if (colpath) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(bk + i) * kBRow + bc] = rb[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(ak + i) * kBRow + ar] = rb[i];
+        }
+        __syncthreads();
+        if (ch + 1 < nchunk) gload((ch + 1) * kDKC);
+#pragma unroll
+        for (int kk = 0; kk < kDKC; kk += 4) {
+            const double* Ak = As + (kk + lk) * kBRow + wr + li;
+            const double* Bk = Bs + (kk + lk) * kBRow + wc + li;
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = Ak[16 * i];
+                b[i] = Bk[16 * i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // D[i][j] of a block: element v of lane 16 g + j holds row 4 v + g
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t col = col0 + wc + 16 * j + li;
+        if (col >= cols) continue;
+        int64_t obase = 0, rstride = 1;
+        if (colpath) {
+            const int64_t l = col / R, r = col - l * R;
+            obase = l * (int64_t)nout * R + r;
+            rstride = R;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + wr + 16 * i + 4 * v + lk;
+                if (row >= rows) continue;
+                const int64_t o = colpath ? obase + row * rstride : row * nout + col;
+                double val = alpha * acc[i][j][v];
+                if (beta != 0.0) val += beta * Z[o];
+                Y[o] = val;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static unsigned elem_grid(int64_t n) {
@@ -438,6 +568,12 @@ hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const do
     const int64_t cols = (R > 1) ? L * R : nout;
     const int64_t tiles = ((rows + kDT - 1) / kDT) * ((cols + kDT - 1) / kDT);
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t tiles128 = ((rows + kBT - 1) / kBT) * ((cols + kBT - 1) / kBT);
+    if (lp == 0 && rows >= kBT && cols >= kBT && tiles128 >= 1024) {
+        hipLaunchKernelGGL(modeprod128_kernel, dim3((unsigned)tiles128), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
+                           nout, R, alpha, beta, upper && nin == nout ? 1 : 0);
+        return hipGetLastError();
+    }
     if (lp == 2)
         hipLaunchKernelGGL(modeprod_kernel<2>, dim3((unsigned)tiles), dim3(kDThreads), 0, st, X, Y, Z, M, L, nin,
                            nout, R, alpha, beta, upper && nin == nout ? 1 : 0);
