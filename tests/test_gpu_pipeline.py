@@ -44,6 +44,17 @@ def test_general_matches_oracle(shape, seed):
     assert info["host_seconds"] >= 0
 
 
+def test_general_ragged_large_tiles():
+    """(300, 260, 250): every mode product has at least 1024 tiles of
+    128x128 and ragged edges in both tile dimensions (the large-tile mode
+    product; mode 2 takes its R = 1 path), against the oracle."""
+    p = ti.laplace_dense((300, 260, 250), seed=10)
+    print("case general ragged large tiles", flush=True)
+    X = host(tt().solve_general(p["A"], dev(p["B"])))
+    Xo = oracle.dense_solve_with_factors(p["Q"], p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+
+
 def test_general_in_place():
     p = ti.laplace_dense((33, 20, 27), seed=7)
     B = dev(p["B"])
