@@ -177,7 +177,8 @@ int partition_mode(int64_t n, const double* T, int b, std::vector<int32_t>& bst,
 hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
                        const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
                        const int* bmax, int maxtup, int maxcpl, int maxH, hipStream_t st);
-// Leaves of the second operator class (tt_leaf2.hip), one wave per block.
+// Leaves of the second operator class (tt_leaf2.hip): one wave per block of
+// at most 1000 unknowns, else 256 threads.
 hipError_t launch_leaf2(int D, const LeafDesc* leaves, int64_t first, int64_t count, const ProbDesc* probs,
                         const LeafShape* shapes, const uint16_t* ents, const int32_t* hoffs, int* status,
                         const int* bmax, hipStream_t st);
