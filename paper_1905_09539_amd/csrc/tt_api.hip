@@ -2011,12 +2011,8 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
         for (size_t ti = 0; ti < s.tasks.size(); ++ti) {
             const UpdDesc& t = s.tasks[ti];
             const bool right = (t.mode == D - 1);
-            int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
-            int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
-            if (t.M <= 16) {
-                na = (t.P + 4 * kTile - 1) / (4 * kTile);
-                nb = 1;
-            }
+            int na = 1, nb = 1;
+            upd_tile_grid(t, right, na, nb);
             hit[ti].assign((size_t)na * nb, 0);
             tiles_b[ti] = nb;
         }

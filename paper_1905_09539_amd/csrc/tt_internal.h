@@ -106,11 +106,28 @@ struct UpdDesc {
     int64_t ostr[3];             // strides of the other modes
 };
 
-// One 64x64 output tile of an update task.
+// One output tile of an update task.
 struct WorkItem {
     int32_t task;
     int16_t ta, tb;              // tile indices (meaning depends on the kernel)
 };
+
+// Output tiles of an update task: na x nb, item (ta, tb) with ta < na and
+// tb < nb.  At most 16 target rows: 16 x 256 tiles (ta: 256 pencil columns);
+// more than 64: 128 target rows x 64 pencil columns; else 64 x 64.  For
+// modes below D - 1, ta counts target rows and tb pencil columns; for the
+// fastest mode (right: MFMA rows are pencil columns) the reverse.
+inline void upd_tile_grid(const UpdDesc& t, bool right, int& na, int& nb) {
+    if (t.M <= 16) {
+        na = (t.P + 4 * kTile - 1) / (4 * kTile);
+        nb = 1;
+        return;
+    }
+    const int th = (t.M > kTile) ? 2 * kTile : kTile;  // target rows per tile
+    const int nr = (t.M + th - 1) / th, nc = (t.P + kTile - 1) / kTile;
+    na = right ? nc : nr;
+    nb = right ? nr : nc;
+}
 
 // One wave of the schedule: the leaf blocks of hyperplane k and the update
 // tiles that became ready after hyperplane k-1.  The two run concurrently

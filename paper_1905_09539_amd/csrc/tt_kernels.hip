@@ -14,14 +14,16 @@ namespace tt {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// Update kernel: one workgroup per 64x64 output tile of one pencil update of
-// the recursion (Algorithm 2's B_1 <- B_1 - X_2 x_mu A_mu(1:k, k+1:n_mu)):
+// Update kernel: one workgroup per output tile of one pencil update of the
+// recursion (Algorithm 2's B_1 <- B_1 - X_2 x_mu A_mu(1:k, k+1:n_mu)):
 //   C[r, c] (+)= sum_k A[r, k] * Bx[k, c]
 // with A = T_mu[r0 + r, k0 + k], Bx[k, c] = X[col_off(c) + (k0 + k) s_mu],
 // and C[r, c] the target element at col_off(c) + (r0 + r) s_mu: X itself for
 // mode 0 (subtract), the accumulator of mode mu otherwise (add, or store for
-// the first contribution).  The 64x64 tile is four 32x32 wave tiles of 2x2
-// MFMA 16x16x4 FP64 blocks; K advances in chunks of 16 staged through LDS.
+// the first contribution).  A 64x64 tile is four 32x32 wave tiles of 2x2
+// MFMA 16x16x4 FP64 blocks (tasks with more than 64 target rows: 128 x 64
+// tiles, two such blocks per wave; at most 16 target rows: 16 x 256 tiles);
+// K advances in chunks of 16 staged through LDS.
 // For the fastest mode (s_mu = 1) the roles are transposed so that the
 // contiguous index runs along the MFMA columns.
 //
@@ -156,6 +158,18 @@ __device__ inline void k_pipeline(int nchunk, Load&& load, Stage&& stage, Comput
     }
 }
 
+// The same K loop with one chunk in flight (set 0 only), for tiles whose
+// accumulators leave no registers for a second set.
+template <class Load, class Stage, class Compute>
+__device__ inline void k_single(int nchunk, Load&& load, Stage&& stage, Compute&& compute) {
+    load(0, 0);
+    for (int ch = 0; ch < nchunk; ++ch) {
+        stage(0);
+        if (ch + 1 < nchunk) load(0, (ch + 1) * kKC);
+        compute();
+    }
+}
+
 // Wide tile for updates with at most 16 target rows (the 64x64 tile would
 // leave 3/4 of its MFMA rows idle): 16 target rows x 256 pencil columns, each
 // wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
@@ -282,20 +296,206 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
         }
 }
 
+// The 64-column tile path: TR = 1 gives 64x64 output tiles, TR = 2 tiles of
+// 128 target rows x 64 pencil columns (tasks with more than 64 target rows:
+// each source chunk staged in LDS then feeds twice the MFMA work, and a task
+// re-reads its source panel half as often).  Four waves; each wave owns
+// 32 TR x 32 of the tile as TR stacked 32x32 blocks of 2x2 MFMA 16x16 tiles
+// (left path: stacked along the target rows, the MFMA rows; right path:
+// along the target rows, the MFMA columns).
+template <int LP, int TR>
+__device__ inline void upd_tile(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
+                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
+                                bool right, bool store, const gdouble* B0, double sgn, double* smem,
+                                int64_t* colOff) {
+    constexpr int kRows = kTile * TR;  // target rows of the tile
+    // LDS: the [row][k] blocks (pitch kRkRow) of up to kRows rows and the
+    // 16 x 80 [k][c] pencil block
+    constexpr int kBOff = (kRows * kRkRow > kKC * kLdsRow) ? kRows * kRkRow : kKC * kLdsRow;
+    static_assert(kBOff + kRows * kRkRow <= kUpdSmemDoubles && kBOff + kKC * kLdsRow <= kUpdSmemDoubles,
+                  "update tile exceeds its LDS buffer");
+    double* As = smem;
+    double* Bs = smem + kBOff;
+    const int tid = threadIdx.x;
+    const int col0 = (right ? wi.ta : wi.tb) * kTile;  // pencil columns
+    const int row0 = (right ? wi.tb : wi.ta) * kRows;  // target rows in mode mu
+
+    if (tid < kTile) {
+        int c = col0 + tid;
+        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    typename MfmaAcc<LP>::type acc[TR][2][2];
+#pragma unroll
+    for (int h = 0; h < TR; ++h)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[h][i][j] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
+    const int nchunk = (t.K + kKC - 1) / kKC;
+    // two chunks in flight for 64-row tiles, one for 128-row tiles (their
+    // accumulators take twice the registers)
+    auto k_loop = [](int nch, auto&& load, auto&& stage, auto&& compute) {
+        if constexpr (TR == 1)
+            k_pipeline(nch, load, stage, compute);
+        else
+            k_single(nch, load, stage, compute);
+    };
+
+    if (!right) {
+        // MFMA rows = target rows r, MFMA columns = pencil columns c; wave
+        // rows wr .. wr + 32 TR, columns wc .. wc + 32.
+        // loaders: A (T rows, contiguous along K): rows tid/8 + 32 j, K pair
+        // tid%8, staged as [r][k]; B (pencil data): column tid%64 (one column
+        // per lane: consecutive lanes read consecutive memory within a
+        // pencil row), K rows 4*(tid/64)..+3
+        const int wr = (wave >> 1) * 32 * TR, wc = (wave & 1) * 32;
+        const int la_r = tid >> 3, la_k = 2 * (tid & 7);
+        const int lb_c = tid & 63, lb_k = (tid >> 6) * 4;
+        double ra0[4 * TR], rb0[4], ra1[4 * TR], rb1[4];  // two chunks in flight
+        const bool bval = (col0 + lb_c) < t.P;
+        const gdouble* Bcol = X + colOff[lb_c] + (int64_t)(t.k0 + lb_k) * smu;
+        bool aval[2 * TR];
+        const gdouble* Arow[2 * TR];
+#pragma unroll
+        for (int j = 0; j < 2 * TR; ++j) {
+            aval[j] = (row0 + la_r + 32 * j) < t.M;
+            Arow[j] = T + (int64_t)(t.r0 + row0 + la_r + 32 * j) * nmu + t.k0 + la_k;
+        }
+        auto gload = [&](double (&ra)[4 * TR], double (&rb)[4], int kc) {
+#pragma unroll
+            for (int j = 0; j < 2 * TR; ++j)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) ra[2 * j + e] = *pick(aval[j] && kc + la_k + e < t.K, Arow[j] + kc + e);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                rb[i] = *pick(bval && kc + lb_k + i < t.K, Bcol + (int64_t)(kc + i) * smu);
+        };
+        auto stage = [&](const double (&ra)[4 * TR], const double (&rb)[4]) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 2 * TR; ++j)
+#pragma unroll
+                for (int e = 0; e < 2; ++e) As[(la_r + 32 * j) * kRkRow + la_k + e] = ra[2 * j + e];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Bs[(lb_k + i) * kLdsRow + lb_c] = rb[i];
+            __syncthreads();
+        };
+        k_loop(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() {
+#pragma unroll
+                for (int h = 0; h < TR; ++h) mfma_chunk_l<LP, true, false>(As, Bs, wr + 32 * h, wc, li, lk, acc[h]);
+            });
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = wc + 16 * j + li;
+            if (col0 + c >= t.P) continue;
+            const int64_t coff = colOff[c];
+#pragma unroll
+            for (int h = 0; h < TR; ++h)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = wr + 32 * h + 16 * i + mfma_row<LP>(v, lk);
+                        if (row0 + r < t.M) {
+                            const int64_t o = coff + (int64_t)(t.r0 + row0 + r) * smu;
+                            const double val = sgn * (double)acc[h][i][j][v];
+                            C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
+                        }
+                    }
+        }
+    } else {
+        // MFMA rows = pencil columns c, MFMA columns = target rows r; wave
+        // columns wr .. wr + 32, target rows wc .. wc + 32 TR.  Both operands
+        // are contiguous along K: eight lanes share a row of either block
+        // (one 128-byte line per eight lanes) and the blocks are staged as
+        // [row][k] with an odd pitch.  Thread tid takes rows tid / 8 + 32 j,
+        // K pair tid % 8.
+        const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32 * TR;
+        const int lr = tid >> 3, rk = 2 * (tid & 7);
+        const gdouble* Xr[2];
+        const gdouble* Tr[2 * TR];
+        bool cval[2], rval[2 * TR];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = lr + 32 * j;
+            cval[j] = (col0 + q) < t.P;
+            Xr[j] = X + colOff[q] + t.k0 + rk;
+        }
+#pragma unroll
+        for (int j = 0; j < 2 * TR; ++j) {
+            const int q = lr + 32 * j;
+            rval[j] = (row0 + q) < t.M;
+            Tr[j] = T + (int64_t)(t.r0 + row0 + q) * nmu + t.k0 + rk;
+        }
+        double ra0[4], rb0[4 * TR], ra1[4], rb1[4 * TR];  // two chunks in flight
+        auto gload = [&](double (&ra)[4], double (&rb)[4 * TR], int kc) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool kv = kc + rk + e < t.K;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) ra[2 * j + e] = *pick(cval[j] && kv, Xr[j] + kc + e);
+#pragma unroll
+                for (int j = 0; j < 2 * TR; ++j) rb[2 * j + e] = *pick(rval[j] && kv, Tr[j] + kc + e);
+            }
+        };
+        auto stage = [&](const double (&ra)[4], const double (&rb)[4 * TR]) {
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) As[(lr + 32 * j) * kRkRow + rk + e] = ra[2 * j + e];
+#pragma unroll
+                for (int j = 0; j < 2 * TR; ++j) Bs[(lr + 32 * j) * kRkRow + rk + e] = rb[2 * j + e];
+            }
+            __syncthreads();
+        };
+        k_loop(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() {
+#pragma unroll
+                for (int h = 0; h < TR; ++h) mfma_chunk_l<LP, true, true>(As, Bs, wr, wc + 32 * h, li, lk, acc[h]);
+            });
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = wr + 16 * i + mfma_row<LP>(v, lk);
+                if (col0 + c >= t.P) continue;
+                const int64_t coff = colOff[c];
+#pragma unroll
+                for (int h = 0; h < TR; ++h)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int r = wc + 32 * h + 16 * j + li;
+                        if (row0 + r < t.M) {
+                            const int64_t o = coff + t.r0 + row0 + r;
+                            const double val = sgn * (double)acc[h][i][j][v];
+                            C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
+                        }
+                    }
+            }
+    }
+}
+
 template <int LP>
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))) void upd_kernel(const UpdDesc* __restrict__ tasks,
                                                           const WorkItem* __restrict__ items,
                                                           int64_t first,
                                                           const ProbDesc* __restrict__ probs, int D) {
-    // one LDS buffer, carved per path: 64x64 tiles a 64 x 17 T block ([r][k])
-    // at As and, at Bs, a 16 x 80 pencil block ([k][c]; fastest mode: a
-    // 64 x 17 [c][k] block); wide tiles a 16 x 17 T block and a 16 x 272
-    // pencil block (fastest mode: 256 x 17)
+    // one LDS buffer, carved per path: 64-column tiles a 64 TR x 17 T block
+    // ([r][k]) and a 16 x 80 pencil block ([k][c]; fastest mode: a 64 x 17
+    // [c][k] block); wide tiles a 16 x 17 T block and a 16 x 272 pencil
+    // block (fastest mode: 256 x 17)
     __shared__ double smem[kUpdSmemDoubles];
     __shared__ int64_t colOff[4 * kTile];
-    double* As = smem;
-    double* Bs = smem + kKC * kLdsRow;
-    const int tid = threadIdx.x;
     const WorkItem wi = items[first + blockIdx.x];
     if (wi.task < 0) return;  // padding of the per-XCD tile layout (uniform)
     const UpdDesc t = tasks[wi.task];
@@ -316,145 +516,10 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
         upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, smem + kWideTDoubles, colOff);
         return;
     }
-    const int col0 = (right ? wi.ta : wi.tb) * kTile;  // pencil columns
-    const int row0 = (right ? wi.tb : wi.ta) * kTile;  // target rows in mode mu
-
-    if (tid < kTile) {
-        int c = col0 + tid;
-        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
-    }
-    __syncthreads();
-
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    const int li = lane & 15, lk = lane >> 4;
-    typename MfmaAcc<LP>::type acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
-    const int nchunk = (t.K + kKC - 1) / kKC;
-
-    if (!right) {
-        // MFMA rows = target rows r, MFMA columns = pencil columns c.
-        // loaders: A (T rows, contiguous along K): rows tid/8 and 32 + tid/8,
-        // K pair tid%8, staged as [r][k]; B (pencil data): column tid%64 (one
-        // column per lane: consecutive lanes read consecutive memory within
-        // a pencil row), K rows 4*(tid/64)..+3
-        const int la_r = tid >> 3, la_k = 2 * (tid & 7);
-        const int lb_c = tid & 63, lb_k = (tid >> 6) * 4;
-        double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
-        const bool bval = (col0 + lb_c) < t.P;
-        const gdouble* Bcol = X + colOff[lb_c] + (int64_t)(t.k0 + lb_k) * smu;
-        bool aval[2];
-        const gdouble* Arow[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            aval[j] = (row0 + la_r + 32 * j) < t.M;
-            Arow[j] = T + (int64_t)(t.r0 + row0 + la_r + 32 * j) * nmu + t.k0 + la_k;
-        }
-        auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) ra[2 * j + e] = *pick(aval[j] && kc + la_k + e < t.K, Arow[j] + kc + e);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                rb[i] = *pick(bval && kc + lb_k + i < t.K, Bcol + (int64_t)(kc + i) * smu);
-        };
-        auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) As[(la_r + 32 * j) * kRkRow + la_k + e] = ra[2 * j + e];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) Bs[(lb_k + i) * kLdsRow + lb_c] = rb[i];
-            __syncthreads();
-        };
-        k_pipeline(
-            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
-            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
-            [&]() { mfma_chunk_l<LP, true, false>(As, Bs, wr, wc, li, lk, acc); });
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int c = wc + 16 * j + li;
-            if (col0 + c >= t.P) continue;
-            const int64_t coff = colOff[c];
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = wr + 16 * i + mfma_row<LP>(v, lk);
-                    if (row0 + r < t.M) {
-                        const int64_t o = coff + (int64_t)(t.r0 + row0 + r) * smu;
-                        const double val = sgn * (double)acc[i][j][v];
-                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
-                    }
-                }
-        }
-    } else {
-        // MFMA rows = pencil columns c, MFMA columns = target rows r.  Both
-        // operands are contiguous along K: eight lanes share a row of either
-        // block (one 128-byte line per eight lanes) and the blocks are staged
-        // as [row][k] with an odd pitch.  Thread tid takes rows tid / 8 and
-        // 32 + tid / 8, K pair tid % 8.
-        const int lr = tid >> 3, rk = 2 * (tid & 7);
-        const gdouble* Xr[2];
-        const gdouble* Tr[2];
-        bool cval[2], rval[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = lr + 32 * j;
-            cval[j] = (col0 + q) < t.P;
-            rval[j] = (row0 + q) < t.M;
-            Xr[j] = X + colOff[q] + t.k0 + rk;
-            Tr[j] = T + (int64_t)(t.r0 + row0 + q) * nmu + t.k0 + rk;
-        }
-        double ra0[4], rb0[4], ra1[4], rb1[4];  // two chunks in flight
-        auto gload = [&](double (&ra)[4], double (&rb)[4], int kc) {
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    const bool kv = kc + rk + e < t.K;
-                    ra[2 * j + e] = *pick(cval[j] && kv, Xr[j] + kc + e);
-                    rb[2 * j + e] = *pick(rval[j] && kv, Tr[j] + kc + e);
-                }
-        };
-        auto stage = [&](const double (&ra)[4], const double (&rb)[4]) {
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    As[(lr + 32 * j) * kRkRow + rk + e] = ra[2 * j + e];
-                    Bs[(lr + 32 * j) * kRkRow + rk + e] = rb[2 * j + e];
-                }
-            __syncthreads();
-        };
-        k_pipeline(
-            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
-            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
-            [&]() { mfma_chunk_l<LP, true, true>(As, Bs, wr, wc, li, lk, acc); });
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int c = wr + 16 * i + mfma_row<LP>(v, lk);
-                if (col0 + c >= t.P) continue;
-                const int64_t coff = colOff[c];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int r = wc + 16 * j + li;
-                    if (row0 + r < t.M) {
-                        const int64_t o = coff + t.r0 + row0 + r;
-                        const double val = sgn * (double)acc[i][j][v];
-                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
-                    }
-                }
-            }
-    }
+    if (t.M > kTile)  // uniform; the planner sizes the task's tiles by the same rule
+        upd_tile<LP, 2>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, colOff);
+    else
+        upd_tile<LP, 1>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, colOff);
 }
 
 __global__ void zero_int_kernel(int* p, int count) {

@@ -420,13 +420,17 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
         // update tiles triggered by the previous wave
         wv.item_first = (int64_t)s.items.size();
         if (w >= 1) {
-            // longest tiles first (the work of a tile grows with K), so that
+            // longest tiles first (the work of a tile grows with K and its
+            // height), so that
             // the launch does not end on a few long tiles; tiles of one task
             // stay adjacent
             order = triggered[(size_t)(w - 1)];
-            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-                return s.tasks[(size_t)a].K > s.tasks[(size_t)b].K;
-            });
+            auto tile_work = [&](int32_t k) {  // K x (target rows of a tile / 64)
+                const UpdDesc& t = s.tasks[(size_t)k];
+                return (int64_t)t.K * ((t.M > kTile) ? 2 : 1);
+            };
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int32_t a, int32_t b) { return tile_work(a) > tile_work(b); });
             // Workgroups go to the XCDs round-robin (workgroup i to XCD i % 8):
             // the tiles of one task that read the same source panel (same
             // pencil columns) are dealt to one XCD, so the panel is fetched
@@ -437,12 +441,8 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             for (int32_t tid : order) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
                 const bool right = (t.mode == D - 1);
-                int na = right ? (t.P + kTile - 1) / kTile : (t.M + kTile - 1) / kTile;
-                int nb = right ? (t.M + kTile - 1) / kTile : (t.P + kTile - 1) / kTile;
-                if (t.M <= 16) {  // wide tiles: 16 target rows x 256 pencil columns
-                    na = (t.P + 4 * kTile - 1) / (4 * kTile);
-                    nb = 1;
-                }
+                int na = 1, nb = 1;
+                upd_tile_grid(t, right, na, nb);
                 // a group: the tiles sharing pencil columns (b for the left
                 // path, a for the right path; every wide tile alone)
                 const int ng = (t.M <= 16) ? na : (right ? na : nb);
