@@ -64,6 +64,21 @@ def test_leaf_sizes(nmin):
     assert rel(X, Xo) <= TOL
 
 
+@pytest.mark.parametrize("shape,nmin,seed", [
+    ((200, 150, 180), 10, 31), ((140, 9, 150), 8, 34), ((90, 20, 24, 18), 5, 32), ((20, 18, 24, 90), 5, 33),
+])
+def test_tall_update_tiles(shape, nmin, seed):
+    """Updates with more than 64 target rows (tiles of 128 target rows):
+    targets of ~70-150 rows, ragged in the target rows, in the pencil
+    columns (products of ~8-10-row blocks) and in K, on the strided modes
+    and on the fastest mode; element by element against the oracle."""
+    p = ti.laplace_tri(shape, seed=seed, bumps="random")
+    print("case tall tiles", shape, nmin, seed, flush=True)
+    X = gpu_solve(p["T"], p["B"], nmin=nmin)
+    Xo = oracle.lap_solve(p["T"], p["B"])
+    assert rel(X, Xo) <= TOL
+
+
 def test_closed_form_diagonal_full_size():
     """Diagonal T_mu: X = B / (a1_i + a2_j + a3_k), at n = 512."""
     n = 512
