@@ -199,6 +199,13 @@ __device__ inline bool tuple_solve16(const double (&Dm)[4][4], double c, double 
     return ok;
 }
 
+// The same solve as a call: the 512-thread order-4 leaf has half the
+// registers of the 256-thread one, and inlined, the sixteen-unknown solve
+// would spill registers of the whole kernel.
+__device__ __attribute__((noinline)) bool tuple_solve16_call(const double (&Dm)[4][4], double c, double (&b)[16]) {
+    return tuple_solve16(Dm, c, b);
+}
+
 // Exact e / s for 0 <= e < 2^16 and s >= 1, from rs = 1.0f / s: the value
 // (e + 0.5) / s < 2^16 / s lies at least 0.5 / s from an integer, while the
 // float product is off by at most 2^-23 * 2^16 / s = 2^-7 / s.
@@ -239,7 +246,7 @@ __device__ inline double lds_dot_pair(const double* L, int to, int xo, int xs, i
 
 // Small system of a tuple with 2x2 blocks in some modes (a: first rows,
 // w: widths); the right-hand sides of its unknowns are already in Xs.
-template <int D>
+template <int D, bool CALL16 = false>
 __device__ inline bool coupled_solve(double* Xs, double* const (&Ts)[D], const int (&tp)[D], const int (&ls)[D],
                                      const int (&a)[D], const int (&w)[D], int e0) {
     int ne = 1;
@@ -311,7 +318,7 @@ __device__ inline bool coupled_solve(double* Xs, double* const (&Ts)[D], const i
             double r16[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) r16[q] = rb[q];
-            if (!tuple_solve16(Dm, cdiag, r16)) ok = false;
+            if (!(CALL16 ? tuple_solve16_call(Dm, cdiag, r16) : tuple_solve16(Dm, cdiag, r16))) ok = false;
 #pragma unroll
             for (int q = 0; q < 16; ++q) Xs[eq[q]] = r16[q];
         }
@@ -380,9 +387,11 @@ __device__ inline bool tuple_inverse(double* const (&Ts)[D], const int (&tp)[D],
 
 // NT threads per leaf: 256 for blocks up to 16^3 (three such workgroups share
 // a CU: ~50 KB of LDS each), 64 (one wave, no cross-wave barriers) for blocks
-// up to 10^3, whose hyperplanes hold at most ~75 unknowns.  The order-3
-// kernel is held to three waves per SIMD worth of registers; order 4 keeps
-// its 16-unknown tuple solve in registers (one wave per SIMD).
+// up to 10^3, whose hyperplanes hold at most ~75 unknowns; 512 (two lanes per
+// unknown) for launches with few leaves.  The order-3 kernel is held to
+// three waves per SIMD worth of registers; the 256-thread order-4 kernel
+// keeps its 16-unknown tuple solve in registers (one wave per SIMD), the
+// 512-thread one (two waves per SIMD) calls it out of line.
 template <int D, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 : 3))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
                                                       const ProbDesc* __restrict__ probs,
@@ -835,7 +844,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                 int e0 = 0;
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) e0 += a[mu] * ls[mu];
-                if (!coupled_solve<D>(Xs, Ts, tp, ls, a, w, e0)) ok = false;
+                if (!coupled_solve<D, (D == 4 && NT > kLeafNT)>(Xs, Ts, tp, ls, a, w, e0)) ok = false;
             }
         }
         __syncthreads();
@@ -886,22 +895,28 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     const bool small = geom.cap <= 1000;
     // a launch with at most one leaf per CU gives each order-3 leaf 512
     // threads (two lanes per unknown): the CU would otherwise hold one
-    // 256-thread leaf and idle
+    // 256-thread leaf and idle; order 4 (whose 512-thread kernel spills
+    // registers) takes it with at most one leaf per two CUs
     int cus = 0, dev = 0;  // CUs of the current device (queried per launch: a process may drive several GPUs)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 0;
-    const bool wide = D == 3 && !small && cus > 0 && count <= cus;
+    const bool wide = !small && cus > 0 && count <= ((D == 4) ? cus / 2 : cus);
     dim3 grid((unsigned)count), block(small ? 64 : (wide ? kLeafNTWide : kLeafNT));
     const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64>
                                        : (wide ? (const void*)leaf_kernel<3, kLeafNTWide>
                                                : (const void*)leaf_kernel<3, kLeafNT>))
-                              : (small ? (const void*)leaf_kernel<4, 64> : (const void*)leaf_kernel<4, kLeafNT>);
+                              : (small ? (const void*)leaf_kernel<4, 64>
+                                       : (wide ? (const void*)leaf_kernel<4, kLeafNTWide>
+                                               : (const void*)leaf_kernel<4, kLeafNT>));
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    if (wide)
+    if (wide && D == 4)
+        hipLaunchKernelGGL((leaf_kernel<4, kLeafNTWide>), grid, block, lds, st, leaves, first, probs, shapes, ents,
+                           hoffs, status, geom);
+    else if (wide)
         hipLaunchKernelGGL((leaf_kernel<3, kLeafNTWide>), grid, block, lds, st, leaves, first, probs, shapes, ents,
                            hoffs, status, geom);
     else if (D == 3 && small)
