@@ -13,7 +13,7 @@ namespace tt {
 
 constexpr int kMaxD = 4;          // internal order (d < 3 is promoted to 3)
 constexpr int kLeafNT = 256;      // threads of the workgroup owning one leaf block
-constexpr int kLeafNTWide = 512;  // the same for launches with at most one leaf per CU
+constexpr int kLeafNTWide = 512;  // the same for launches with at most one leaf per CU (order 4: per two CUs)
 constexpr int kMaxLeaf = 24;      // largest leaf block edge
 constexpr int kUpdThreads = 256;  // one workgroup per 64x64 update tile
 constexpr int kTile = 64;
