@@ -1927,35 +1927,50 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
             int slo, shi;
         };
         std::vector<Delivery> deliveries;
-        for (int64_t q = 0; q < wv.item_count; ++q) {
+        for (int64_t q = 0; q < wv.item_count && !bad; ++q) {
             const WorkItem& w = s.items[(size_t)(wv.item_first + q)];
             if (w.task < 0) continue;  // padding
-            if (task_seen[(size_t)w.task]) continue;
-            task_seen[(size_t)w.task] = 1;
-            seen_tasks.push_back(w.task);
-            const UpdDesc& t = s.tasks[(size_t)w.task];
-            const int mu = t.mode;
-            int I[kMaxD];
-            int64_t rem = t.xbase;
-            for (int nu = 0; nu < D; ++nu) {
-                if (nu == mu) { I[nu] = 0; continue; }
-                int64_t idx = rem / hp.stride[nu];
-                rem -= idx * hp.stride[nu];
-                I[nu] = find_blk(nu, idx);
-                if (I[nu] >= hp.m[nu]) bad = 1;
+            if ((size_t)w.task >= s.tasks.size()) { bad = 1; break; }
+            // a 16 x 256 tile serves tasks w.task .. w.task + w.tb, which
+            // must differ in their pencil only
+            const UpdDesc& t0 = s.tasks[(size_t)w.task];
+            const int npk = (t0.M <= 16) ? w.tb + 1 : 1;
+            if (npk < 1 || npk > upd_wide_slots(t0.P) || (size_t)w.task + npk > s.tasks.size()) { bad = 1; break; }
+            for (int j = 1; j < npk; ++j) {
+                const UpdDesc& tj = s.tasks[(size_t)(w.task + j)];
+                if (tj.prob != t0.prob || tj.mode != t0.mode || tj.r0 != t0.r0 || tj.M != t0.M || tj.k0 != t0.k0 ||
+                    tj.K != t0.K || tj.P != t0.P || (tj.flags & 1) != (t0.flags & 1))
+                    bad = 1;
             }
-            if (bad) break;
-            const int lo = find_blk(mu, t.r0), hi_t = find_blk(mu, t.r0 + t.M);
-            const int slo = find_blk(mu, t.k0), shi = find_blk(mu, t.k0 + t.K);
-            if (hi_t > hp.m[mu] || shi > hp.m[mu] || hi_t > slo) { bad = 1; break; }
-            for (int b = slo; b < shi; ++b) {
-                I[mu] = b;
-                if (!solved[(size_t)lin(I)]) bad = 1;
-            }
-            for (int b = lo; b < hi_t; ++b) {
-                I[mu] = b;
-                if (solved[(size_t)lin(I)] || wave_of(I) <= (int64_t)k) bad = 1;
-                deliveries.push_back({lin(I) * D + mu, slo, shi});
+            for (int j = 0; j < npk && !bad; ++j) {
+                const int32_t ti = w.task + j;
+                if (task_seen[(size_t)ti]) continue;
+                task_seen[(size_t)ti] = 1;
+                seen_tasks.push_back(ti);
+                const UpdDesc& t = s.tasks[(size_t)ti];
+                const int mu = t.mode;
+                int I[kMaxD];
+                int64_t rem = t.xbase;
+                for (int nu = 0; nu < D; ++nu) {
+                    if (nu == mu) { I[nu] = 0; continue; }
+                    int64_t idx = rem / hp.stride[nu];
+                    rem -= idx * hp.stride[nu];
+                    I[nu] = find_blk(nu, idx);
+                    if (I[nu] >= hp.m[nu]) bad = 1;
+                }
+                if (bad) break;
+                const int lo = find_blk(mu, t.r0), hi_t = find_blk(mu, t.r0 + t.M);
+                const int slo = find_blk(mu, t.k0), shi = find_blk(mu, t.k0 + t.K);
+                if (hi_t > hp.m[mu] || shi > hp.m[mu] || hi_t > slo) { bad = 1; break; }
+                for (int b = slo; b < shi; ++b) {
+                    I[mu] = b;
+                    if (!solved[(size_t)lin(I)]) bad = 1;
+                }
+                for (int b = lo; b < hi_t; ++b) {
+                    I[mu] = b;
+                    if (solved[(size_t)lin(I)] || wave_of(I) <= (int64_t)k) bad = 1;
+                    deliveries.push_back({lin(I) * D + mu, slo, shi});
+                }
             }
         }
         for (int32_t t : seen_tasks) task_seen[(size_t)t] = 0;
@@ -2019,11 +2034,17 @@ int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int n
         for (const WorkItem& w : s.items) {
             if (w.task < 0) continue;
             if ((size_t)w.task >= s.tasks.size()) { bad = 1; break; }
-            auto& h = hit[(size_t)w.task];
-            const int nb = tiles_b[(size_t)w.task];
-            const size_t at = (size_t)w.ta * nb + w.tb;
-            if (w.ta < 0 || w.tb < 0 || w.tb >= nb || at >= h.size() || h[at]) { bad = 1; break; }
-            h[at] = 1;
+            const bool wide = s.tasks[(size_t)w.task].M <= 16;
+            const int npk = wide ? w.tb + 1 : 1, tb = wide ? 0 : w.tb;
+            if (npk < 1 || (size_t)w.task + npk > s.tasks.size()) { bad = 1; break; }
+            for (int j = 0; j < npk; ++j) {
+                auto& h = hit[(size_t)(w.task + j)];
+                const int nb = tiles_b[(size_t)(w.task + j)];
+                const size_t at = (size_t)w.ta * nb + tb;
+                if (w.ta < 0 || tb < 0 || tb >= nb || at >= h.size() || h[at]) { bad = 1; break; }
+                h[at] = 1;
+            }
+            if (bad) break;
         }
         for (const auto& h : hit)
             for (uint8_t v : h)

@@ -109,11 +109,19 @@ struct UpdDesc {
 // One output tile of an update task.
 struct WorkItem {
     int32_t task;
-    int16_t ta, tb;              // tile indices (meaning depends on the kernel)
+    int16_t ta, tb;              // tile indices (meaning depends on the kernel);
+                                 // 16 x 256 tiles: tb + 1 consecutive tasks share the tile
 };
 
+// Pencils per 16 x 256 tile: tasks with at most 16 target rows whose
+// pencils have at most 64 (128) columns share a tile four (two) at a time
+// when they agree in everything but the pencil (mode, rows, sources,
+// columns, first-contribution flag); each owns a slot of 64 (128) columns.
+__host__ __device__ inline int upd_wide_slots(int P) { return P <= 64 ? 4 : (P <= 128 ? 2 : 1); }
+
 // Output tiles of an update task: na x nb, item (ta, tb) with ta < na and
-// tb < nb.  At most 16 target rows: 16 x 256 tiles (ta: 256 pencil columns);
+// tb < nb.  At most 16 target rows: 16 x 256 tiles (ta: 256 pencil columns;
+// nb = 1, the item's tb counts the other tasks sharing the tile);
 // more than 64: 128 target rows x 64 pencil columns; else 64 x 64.  For
 // modes below D - 1, ta counts target rows and tb pencil columns; for the
 // fastest mode (right: MFMA rows are pencil columns) the reverse.

@@ -174,19 +174,28 @@ __device__ inline void k_single(int nchunk, Load&& load, Stage&& stage, Compute&
 // leave 3/4 of its MFMA rows idle): 16 target rows x 256 pencil columns, each
 // wave a 16 x 64 strip of four 16x16 MFMA blocks.  Left path: MFMA rows are
 // the target rows; right path (fastest mode): MFMA rows are pencil columns.
+// Pencils of at most 128 (64) columns share a tile: tasks wi.task ..
+// wi.task + wi.tb, which differ only in their pencil, each own a slot of 128
+// (64) columns.  colOff holds -1 for a column outside every pencil.
 template <int LP>
-__device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
-                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
-                                bool right, bool store, const gdouble* B0, double sgn, double* As, double* Bs,
-                                int64_t* colOff) {
+__device__ inline void upd_wide(const UpdDesc* __restrict__ tasks, const UpdDesc& t, const WorkItem& wi,
+                                const gdouble* __restrict__ X, gdouble* __restrict__ C,
+                                const gdouble* __restrict__ T, int64_t nmu, int64_t smu, bool right, bool store,
+                                const gdouble* B0, double sgn, double* As, double* Bs, int64_t* colOff) {
     constexpr int kW = 4 * kTile;   // 256 pencil columns
     constexpr int kWRow = kW + 16;  // LDS row pitch of the 256-wide operand
     constexpr int kTRow = 17;       // LDS pitch of the 16x16 T block (odd: conflict-free staging)
     const int tid = threadIdx.x;
     const int col0 = wi.ta * kW;
     {
-        const int c = col0 + tid;
-        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
+        // column tid: slot tid >> sh, column tid & (2^sh - 1) of that slot's
+        // pencil (one slot of 256 columns: this task, from col0)
+        const int g = upd_wide_slots(t.P);  // uniform
+        const int sh = (g == 4) ? 6 : ((g == 2) ? 7 : 8);
+        const int slot = tid >> sh;
+        const int c = (g == 1) ? col0 + tid : tid & ((1 << sh) - 1);
+        const UpdDesc& ts = tasks[wi.task + min(slot, (int)wi.tb)];  // a task of the tile in any case
+        colOff[tid] = (slot <= wi.tb && c < t.P) ? pencil_col_offset(ts, c) : -1;
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
@@ -200,8 +209,8 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
     const int tr = tid >> 4, tk = tid & 15;
     const bool tval = tr < t.M;
     const gdouble* Trow = T + (int64_t)(t.r0 + tr) * nmu + t.k0;
-    const bool cval = (col0 + tid) < t.P;
     const int64_t coff = colOff[tid];
+    const bool cval = coff >= 0;
     // right path (fastest mode): the K run of a column is contiguous, so
     // eight lanes share one column (two doubles each, one 128-byte line per
     // eight lanes) and the block is staged as [c][k] with an odd pitch;
@@ -219,7 +228,7 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
 #pragma unroll
             for (int j = 0; j < kKC / 2; ++j) {
                 const int c = j * 32 + (tid >> 3);
-                const bool cv = col0 + c < t.P;
+                const bool cv = colOff[c] >= 0;
                 const gdouble* xr = X + colOff[c] + t.k0 + kc + rk;
                 rb[2 * j] = *pick(cv && kc + rk < t.K, xr);
                 rb[2 * j + 1] = *pick(cv && kc + rk + 1 < t.K, xr + 1);
@@ -289,7 +298,7 @@ __device__ inline void upd_wide(const UpdDesc& t, const WorkItem& wi, const gdou
             const int i = mfma_row<LP>(v, lk);
             const int c = wave * 64 + b * 16 + (right ? i : li);
             const int r = right ? li : i;
-            if (col0 + c >= t.P || r >= t.M) continue;
+            if (colOff[c] < 0 || r >= t.M) continue;
             const int64_t o = colOff[c] + (int64_t)(t.r0 + r) * smu;
             const double val = sgn * (double)acc[b][v];
             C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
@@ -513,7 +522,7 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
     // the first mode-0 update of a block starts from the right-hand side B
     const gdouble* B0 = (mode == 0 && store) ? to_global(P.B) : nullptr;
     if (t.M <= 16) {  // uniform over the workgroup
-        upd_wide<LP>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, smem + kWideTDoubles, colOff);
+        upd_wide<LP>(tasks, t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, smem + kWideTDoubles, colOff);
         return;
     }
     if (t.M > kTile)  // uniform; the planner sizes the task's tiles by the same rule

@@ -370,6 +370,10 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
     // Leaf flags: accumulator reads and the adjacent block.
     std::vector<int32_t> order;
     std::vector<std::vector<WorkItem>> xq(8);  // per-XCD tile queues of one wave
+    std::vector<std::vector<int32_t>> units;   // tasks of one item group (see below)
+    std::map<std::array<int64_t, 8>, size_t> open_units;
+    std::vector<UpdDesc> ntasks;               // tasks in item order
+    ntasks.reserve(s.tasks.size());
     for (int64_t w = 0; w < W; ++w) {
         Wave wv;
         wv.leaf_first = (int64_t)s.leaves.size();
@@ -437,9 +441,42 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             // into one L2 instead of several.  Groups fill the least loaded
             // XCD queue in order; the queues are interleaved, and the ragged
             // tail is padded with empty items (task -1).
-            for (auto& q : xq) q.clear();
+            // units: one task, or up to upd_wide_slots(P) tasks with at
+            // most 16 target rows that differ only in their pencil and share
+            // one 16 x 256 tile (filled in order of first appearance)
+            units.clear();
+            open_units.clear();
             for (int32_t tid : order) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
+                const int g = (t.M <= 16) ? upd_wide_slots(t.P) : 1;
+                if (g == 1) {
+                    units.push_back({tid});
+                    continue;
+                }
+                const std::array<int64_t, 8> key = {t.prob, t.mode, t.r0, t.M, t.k0, t.K, t.P, t.flags & 1};
+                auto it = open_units.find(key);
+                if (it == open_units.end()) {
+                    open_units[key] = units.size();
+                    units.push_back({tid});
+                } else {
+                    units[it->second].push_back(tid);
+                    if ((int)units[it->second].size() == g) open_units.erase(it);
+                }
+            }
+            for (auto& q : xq) q.clear();
+            for (const auto& u : units) {
+                // the unit's tasks take consecutive indices of the final task list
+                const int32_t nt = (int32_t)ntasks.size();
+                for (int32_t tid : u) {
+                    const UpdDesc& t = s.tasks[(size_t)tid];
+                    ntasks.push_back(t);
+                    const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
+                    wv.upd_flops += f;
+                    fl_upd += f;
+                    wv.upd_bytes += 8.0 * (((t.flags & 1) && t.mode != 0 ? 1.0 : 2.0) * (double)t.M * t.P +
+                                           (double)t.K * t.P + (double)t.M * t.K);
+                }
+                const UpdDesc& t = s.tasks[(size_t)u[0]];
                 const bool right = (t.mode == D - 1);
                 int na = 1, nb = 1;
                 upd_tile_grid(t, right, na, nb);
@@ -453,17 +490,19 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                         if (xq[y].size() < xq[x].size()) x = y;
                     for (int e = 0; e < gs; ++e) {
                         int a = 0, b = 0;
-                        if (t.M <= 16) a = g;
-                        else if (right) { a = g; b = e; }
-                        else { a = e; b = g; }
-                        xq[x].push_back(WorkItem{tid, (int16_t)a, (int16_t)b});
+                        if (t.M <= 16) {
+                            a = g;
+                            b = (int)u.size() - 1;  // tasks sharing the tile
+                        } else if (right) {
+                            a = g;
+                            b = e;
+                        } else {
+                            a = e;
+                            b = g;
+                        }
+                        xq[x].push_back(WorkItem{nt, (int16_t)a, (int16_t)b});
                     }
                 }
-                const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
-                wv.upd_flops += f;
-                fl_upd += f;
-                wv.upd_bytes += 8.0 * (((t.flags & 1) && t.mode != 0 ? 1.0 : 2.0) * (double)t.M * t.P + (double)t.K * t.P +
-                                       (double)t.M * t.K);
             }
             size_t rounds = 0;
             for (const auto& q : xq) rounds = std::max(rounds, q.size());
@@ -477,6 +516,11 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
         err = "internal: updates triggered by the last wave";
         return TT_EINVAL;
     }
+    if (ntasks.size() != s.tasks.size()) {
+        err = "internal: update tasks lost in the tile layout";
+        return TT_EINVAL;
+    }
+    s.tasks.swap(ntasks);
 
     for (int mu = 0; mu < D; ++mu)
         if (s.bmax[mu] > ((D == 4) ? (1 << kTupBits4) : kMaxLeaf)) {
