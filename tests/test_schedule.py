@@ -136,3 +136,17 @@ def test_workspace_bytes_rejects_bad_shapes():
     assert tt.workspace_bytes((4, 4, 4, 4, 4)) == 0
     assert tt.workspace_bytes((4, -1, 4)) == 0
     assert tt.workspace_bytes((0, 5, 5)) > 0
+
+
+@pytest.mark.parametrize("shape,nmin", [((192, 192, 192), 8), ((40, 36, 44, 30), 5), ((100, 90, 96), 6)])
+def test_small_pencils_share_update_tiles(shape, nmin):
+    """Updates of at most 16 target rows whose pencils have at most 64 (128)
+    columns share a 16 x 256 tile four (two) at a time: far fewer tiles than
+    tasks, and the replay (which checks that the tasks of a shared tile
+    differ only in their pencil and that every task's tiles appear once)
+    finds the schedule complete."""
+    p = ti.laplace_tri(shape, seed=2, bumps="random")
+    info = tt.schedule_info(p["T"], shape, nmin=nmin)
+    assert info["dependency_violation"] == 0
+    assert info["flops"] == oracle.flops_tri(p["T"], shape)
+    assert info["items"] < 0.6 * info["tasks"]
