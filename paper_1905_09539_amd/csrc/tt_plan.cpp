@@ -370,7 +370,11 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
     // Leaf flags: accumulator reads and the adjacent block.
     std::vector<int32_t> order;
     std::vector<std::vector<WorkItem>> xq(8);  // per-XCD tile queues of one wave
-    std::vector<std::vector<int32_t>> units;   // tasks of one item group (see below)
+    struct Unit {                              // tasks sharing the tiles of one item group
+        int32_t task[4];
+        int n;
+    };
+    std::vector<Unit> units;
     std::map<std::array<int64_t, 8>, size_t> open_units;
     std::vector<UpdDesc> ntasks;               // tasks in item order
     ntasks.reserve(s.tasks.size());
@@ -450,25 +454,26 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
                 const int g = (t.M <= 16) ? upd_wide_slots(t.P) : 1;
                 if (g == 1) {
-                    units.push_back({tid});
+                    units.push_back(Unit{{tid, 0, 0, 0}, 1});
                     continue;
                 }
                 const std::array<int64_t, 8> key = {t.prob, t.mode, t.r0, t.M, t.k0, t.K, t.P, t.flags & 1};
                 auto it = open_units.find(key);
                 if (it == open_units.end()) {
                     open_units[key] = units.size();
-                    units.push_back({tid});
+                    units.push_back(Unit{{tid, 0, 0, 0}, 1});
                 } else {
-                    units[it->second].push_back(tid);
-                    if ((int)units[it->second].size() == g) open_units.erase(it);
+                    Unit& un = units[it->second];
+                    un.task[un.n++] = tid;
+                    if (un.n == g) open_units.erase(it);
                 }
             }
             for (auto& q : xq) q.clear();
             for (const auto& u : units) {
                 // the unit's tasks take consecutive indices of the final task list
                 const int32_t nt = (int32_t)ntasks.size();
-                for (int32_t tid : u) {
-                    const UpdDesc& t = s.tasks[(size_t)tid];
+                for (int j = 0; j < u.n; ++j) {
+                    const UpdDesc& t = s.tasks[(size_t)u.task[j]];
                     ntasks.push_back(t);
                     const double f = 2.0 * (double)t.M * (double)t.K * (double)t.P;
                     wv.upd_flops += f;
@@ -476,7 +481,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                     wv.upd_bytes += 8.0 * (((t.flags & 1) && t.mode != 0 ? 1.0 : 2.0) * (double)t.M * t.P +
                                            (double)t.K * t.P + (double)t.M * t.K);
                 }
-                const UpdDesc& t = s.tasks[(size_t)u[0]];
+                const UpdDesc& t = s.tasks[(size_t)u.task[0]];
                 const bool right = (t.mode == D - 1);
                 int na = 1, nb = 1;
                 upd_tile_grid(t, right, na, nb);
@@ -492,7 +497,7 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
                         int a = 0, b = 0;
                         if (t.M <= 16) {
                             a = g;
-                            b = (int)u.size() - 1;  // tasks sharing the tile
+                            b = u.n - 1;  // tasks sharing the tile
                         } else if (right) {
                             a = g;
                             b = e;
