@@ -187,13 +187,13 @@ __device__ inline void upd_wide(const UpdDesc* __restrict__ tasks, const UpdDesc
     constexpr int kTRow = 17;       // LDS pitch of the 16x16 T block (odd: conflict-free staging)
     const int tid = threadIdx.x;
     const int col0 = wi.ta * kW;
-    {
-        // column tid: slot tid >> sh, column tid & (2^sh - 1) of that slot's
-        // pencil (one slot of 256 columns: this task, from col0)
-        const int g = upd_wide_slots(t.P);  // uniform
-        const int sh = (g == 4) ? 6 : ((g == 2) ? 7 : 8);
-        const int slot = tid >> sh;
-        const int c = (g == 1) ? col0 + tid : tid & ((1 << sh) - 1);
+    const int g = upd_wide_slots(t.P);  // uniform
+    if (g == 1) {
+        colOff[tid] = (col0 + tid < t.P) ? pencil_col_offset(t, col0 + tid) : -1;
+    } else {
+        // column tid: slot tid >> sh, column tid & (2^sh - 1) of that slot's pencil
+        const int sh = (g == 4) ? 6 : 7;
+        const int slot = tid >> sh, c = tid & ((1 << sh) - 1);
         const UpdDesc& ts = tasks[wi.task + min(slot, (int)wi.tb)];  // a task of the tile in any case
         colOff[tid] = (slot <= wi.tb && c < t.P) ? pencil_col_offset(ts, c) : -1;
     }
