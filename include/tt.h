@@ -377,6 +377,13 @@ int tt_plan_destroy(tt_plan plan);
  * depends on the coefficients' 2x2-block pattern).
  * Errors: as tt_plan_create. */
 int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int nmin, double* out);
+/* The same query for the schedule of either operator class: cls 0 the
+ * Laplace-like equation (2.2) (as tt_schedule_info), cls 1 the second class
+ * of Sec. 3, eq. (3.1), after the C^{-1} reduction, with T_host the
+ * triangular A_mu (its default leaf edge and update tiles differ; out[0..2]
+ * count the Laplace-like flops of the same schedule).
+ * Errors: as tt_schedule_info; TT_EINVAL for another cls. */
+int tt_schedule_info_class(int d, const int64_t* n, const double* const* T_host, int nmin, int cls, double* out);
 
 /* Host-only real Schur decomposition A = U T U^T of Algorithm 1 (Householder
  * Hessenberg reduction, Francis double-shift QR, standardised 2x2 blocks:

@@ -44,7 +44,7 @@ SYMBOLS = [
     "solve_general_tensor", "solve_backward", "solve_tri_tensor_batched",
     "solve_backward_batched", "tt_plan_create", "tt_plan_create_batched", "tt_plan_solve",
     "tt_plan_solve_batched", "tt_plan_status", "tt_plan_flops", "tt_plan_destroy",
-    "tt_schedule_info", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
+    "tt_schedule_info", "tt_schedule_info_class", "tt_plan_profile", "tt_plan_profile_waves", "tt_plan_create_general", "tt_plan_info", "tt_schur_host", "tt_qz_host",
     "tt_plan_create_general_pair", "tt_plan_coefficient_grads", "tt_plan_solve_graph",
     "tt_copy_device", "tt_workspace_bytes", "solve_tri_tensor_noalloc",
     "solve_gsylv_tensor", "solve_gsylv_general_tensor", "tt_plan_create_gsylv", "tt_plan_create_gsylv_general",
@@ -91,6 +91,8 @@ def lib():
         L.tt_plan_destroy.argtypes = [vp]
         L.tt_plan_profile.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.tt_schedule_info.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.tt_schedule_info_class.argtypes = [ctypes.c_int, i64p, vp, ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_double)]
         L.tt_plan_create_general.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i64p, vp, ctypes.POINTER(Opts)]
         L.tt_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.tt_schur_host.argtypes = [ctypes.c_int, vp, vp, vp]
@@ -495,13 +497,14 @@ def copy_device(src, dst, stream=None):
                                 _stream(stream)))
 
 
-def schedule_info(T_host, shape, nmin=0):
+def schedule_info(T_host, shape, nmin=0, cls=0):
     """Host-only: statistics and dependency check of the solve schedule for
-    coefficients given as numpy arrays (no GPU needed)."""
+    coefficients given as numpy arrays (no GPU needed); cls 1: the schedule
+    of the second operator class (tt_schedule_info_class)."""
     Th = [np.ascontiguousarray(t, dtype=np.float64) for t in T_host]
     out = (ctypes.c_double * 14)()
-    _check(lib().tt_schedule_info(len(shape), _shape(shape), _ptr_array([t.ctypes.data for t in Th]),
-                                  int(nmin), out))
+    _check(lib().tt_schedule_info_class(len(shape), _shape(shape), _ptr_array([t.ctypes.data for t in Th]),
+                                        int(nmin), int(cls), out))
     keys = ["flops", "flops_leaf", "flops_update", "waves", "leaves", "tasks", "items", "launches",
             "bmax0", "bmax1", "bmax2", "bmax3", "dependency_violation", "plan_bytes"]
     return dict(zip(keys, list(out)))

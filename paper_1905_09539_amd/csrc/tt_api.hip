@@ -1859,9 +1859,15 @@ int tt_qz_host(int n, const double* A, const double* C, double* S, double* T, do
 // flops_leaf, flops_update, waves, leaves, tasks, work items, launches,
 // bmax[0..3], dependency check (0 = the schedule respects every dependency).
 int tt_schedule_info(int d, const int64_t* n, const double* const* T_host, int nmin, double* out) {
+    return tt_schedule_info_class(d, n, T_host, nmin, 0, out);
+}
+
+int tt_schedule_info_class(int d, const int64_t* n, const double* const* T_host, int nmin, int cls, double* out) {
     if (!out || !T_host) return fail(TT_EINVAL, "NULL argument");
+    if (cls != 0 && cls != 1) return fail(TT_EINVAL, "cls must be 0 (Laplace-like) or 1 (second class)");
     Schedule s;
     s.D = (d == 4) ? 4 : 3;
+    s.cls = cls;
     s.probs.resize(1);
     int rc = describe_problem(d, n, s.D, s.probs[0]);
     if (rc) return rc;

@@ -445,14 +445,17 @@ int build_schedule(Schedule& s, int nmin, std::string& err) {
             // into one L2 instead of several.  Groups fill the least loaded
             // XCD queue in order; the queues are interleaved, and the ragged
             // tail is padded with empty items (task -1).
-            // units: one task, or up to upd_wide_slots(P) tasks with at
-            // most 16 target rows that differ only in their pencil and share
-            // one 16 x 256 tile (filled in order of first appearance)
+            // units: one task, or (second class) up to upd_wide_slots(P)
+            // tasks with at most 16 target rows that differ only in their
+            // pencil and share one 16 x 256 tile (filled in order of first
+            // appearance).  The Laplace-like schedules gain nothing from the
+            // shared tiles (their small pencils are the few through a thin
+            // block) and were measured slower with them at order 5.
             units.clear();
             open_units.clear();
             for (int32_t tid : order) {
                 const UpdDesc& t = s.tasks[(size_t)tid];
-                const int g = (t.M <= 16) ? upd_wide_slots(t.P) : 1;
+                const int g = (t.M <= 16 && s.cls == 1) ? upd_wide_slots(t.P) : 1;
                 if (g == 1) {
                     units.push_back(Unit{{tid, 0, 0, 0}, 1});
                     continue;

@@ -140,13 +140,24 @@ def test_workspace_bytes_rejects_bad_shapes():
 
 @pytest.mark.parametrize("shape,nmin", [((192, 192, 192), 8), ((40, 36, 44, 30), 5), ((100, 90, 96), 6)])
 def test_small_pencils_share_update_tiles(shape, nmin):
-    """Updates of at most 16 target rows whose pencils have at most 64 (128)
-    columns share a 16 x 256 tile four (two) at a time: far fewer tiles than
-    tasks, and the replay (which checks that the tasks of a shared tile
-    differ only in their pencil and that every task's tiles appear once)
-    finds the schedule complete."""
+    """Second-class schedules: updates of at most 16 target rows whose
+    pencils have at most 64 (128) columns share a 16 x 256 tile four (two)
+    at a time, so there are far fewer tiles than tasks, and the replay
+    (which checks that the tasks of a shared tile differ only in their
+    pencil and that every task's tiles appear once) finds the schedule
+    complete.  The Laplace-like schedule of the same shape shares no tile
+    and covers the same tasks."""
     p = ti.laplace_tri(shape, seed=2, bumps="random")
-    info = tt.schedule_info(p["T"], shape, nmin=nmin)
+    info = tt.schedule_info(p["T"], shape, nmin=nmin, cls=1)
     assert info["dependency_violation"] == 0
     assert info["flops"] == oracle.flops_tri(p["T"], shape)
     assert info["items"] < 0.6 * info["tasks"]
+    lap = tt.schedule_info(p["T"], shape, nmin=nmin)
+    assert lap["dependency_violation"] == 0
+    assert lap["tasks"] == info["tasks"] and lap["items"] > info["items"]
+
+
+def test_schedule_info_class_rejects_unknown_class():
+    p = ti.laplace_tri((8, 8, 8), seed=1, bumps="none")
+    with pytest.raises(tt.TTError):
+        tt.schedule_info(p["T"], (8, 8, 8), cls=2)
