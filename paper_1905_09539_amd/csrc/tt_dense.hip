@@ -3,7 +3,9 @@
 //                     Sec. 2 used by the Schur transforms of Algorithm 1
 //                     (B x_mu U_mu^T before the solve, X x_mu U_mu after),
 //                     by the C_mu^{-1} reduction of the pair form and by the
-//                     FP64 residual of iterative refinement;
+//                     FP64 residual of iterative refinement (modes of at
+//                     most 16 rows: modeprod_small_kernel, one thread per
+//                     fibre; large FP64 products: modeprod128_kernel);
 //   gram_batched_kernel - split-K partial sums of P_(mu) Q_(mu)^T for a table
 //                     of (problem, mode) jobs: the coefficient gradients
 //                     -Lam_(mu) X_(mu)^T of the adjoint;
@@ -11,6 +13,7 @@
 //
 // A tensor of shape (n_1..n_d) in C order is viewed, for mode mu, as
 // [L][n_mu][R] with L = prod_{nu<mu} n_nu and R = prod_{nu>mu} n_nu.
+#include <algorithm>
 #include "tt_bf16.h"
 #include "tt_internal.h"
 
@@ -561,9 +564,49 @@ static unsigned elem_grid(int64_t n) {
     return (unsigned)b;
 }
 
+// Mode product of a small mode (nin, nout <= 16), FP64: one thread per fibre
+// (l, r) keeps its nin inputs in registers and forms its nout outputs from M
+// in LDS.  An 8-row mode would fill an eighth of a 64-row MFMA tile; here
+// the pass is bound by HBM (each element read and written once), and
+// consecutive threads take consecutive r, so every load and store of a
+// wave is contiguous when R > 1.
+constexpr int kSmallMode = 16;
+__global__ __launch_bounds__(256) void modeprod_small_kernel(const double* __restrict__ X, double* Y,
+                                                             const double* Z, const double* __restrict__ M,
+                                                             int64_t L, int nin, int nout, int64_t R,
+                                                             double alpha, double beta) {
+    __shared__ double Ms[kSmallMode * kSmallMode];
+    for (int e = threadIdx.x; e < nout * nin; e += blockDim.x) Ms[e] = M[e];
+    __syncthreads();
+    const int64_t nf = L * R;
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = f / R, r = f - l * R;
+        const double* x = X + l * nin * R + r;
+        double xv[kSmallMode];
+#pragma unroll
+        for (int k = 0; k < kSmallMode; ++k) xv[k] = (k < nin) ? x[(int64_t)min(k, nin - 1) * R] : 0.0;
+        const int64_t ob = l * nout * R + r;
+        for (int i = 0; i < nout; ++i) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < kSmallMode; ++k)
+                if (k < nin) acc = fma(Ms[i * nin + k], xv[k], acc);
+            double val = alpha * acc;
+            if (beta != 0.0) val += beta * Z[ob + i * R];
+            Y[ob + i * R] = val;
+        }
+    }
+}
+
 hipError_t launch_modeprod(const double* X, double* Y, const double* Z, const double* M, int64_t L, int nin,
                            int nout, int64_t R, double alpha, double beta, int lp, hipStream_t st, bool upper) {
     if (L <= 0 || R <= 0 || nout <= 0) return hipSuccess;
+    if (lp == 0 && nin <= kSmallMode && nout <= kSmallMode) {
+        const int64_t blocks = std::min<int64_t>((L * R + 255) / 256, 8192);
+        hipLaunchKernelGGL(modeprod_small_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, Z, M, L, nin,
+                           nout, R, alpha, beta);
+        return hipGetLastError();
+    }
     const int64_t rows = (R > 1) ? nout : L;
     const int64_t cols = (R > 1) ? L * R : nout;
     const int64_t tiles = ((rows + kDT - 1) / kDT) * ((cols + kDT - 1) / kDT);
