@@ -569,7 +569,7 @@ static unsigned elem_grid(int64_t n) {
 // in LDS.  An 8-row mode would fill an eighth of a 64-row MFMA tile; here
 // the pass is bound by HBM (each element read and written once), and
 // consecutive threads take consecutive r, so every load and store of a
-// wave is contiguous when R > 1.
+// wave is contiguous when R > 1 (R = 1: staged through LDS).  256 threads.
 constexpr int kSmallMode = 16;
 __global__ __launch_bounds__(256) void modeprod_small_kernel(const double* __restrict__ X, double* Y,
                                                              const double* Z, const double* __restrict__ M,
@@ -578,6 +578,40 @@ __global__ __launch_bounds__(256) void modeprod_small_kernel(const double* __res
     __shared__ double Ms[kSmallMode * kSmallMode];
     for (int e = threadIdx.x; e < nout * nin; e += blockDim.x) Ms[e] = M[e];
     __syncthreads();
+    if (R == 1) {  // uniform
+        // the last mode: fibres are contiguous runs of nin (nout) values, so
+        // 256 fibres go through LDS and the global loads and stores of a
+        // wave stay contiguous
+        __shared__ double buf[256 * kSmallMode];
+        const int tid = threadIdx.x;
+        for (int64_t f0 = (int64_t)blockIdx.x * 256; f0 < L; f0 += (int64_t)gridDim.x * 256) {
+            const int nfb = (int)min((int64_t)256, L - f0);
+            const double* xb = X + f0 * nin;
+            for (int e = tid; e < nfb * nin; e += 256) buf[e] = xb[e];
+            __syncthreads();
+            double xv[kSmallMode];
+#pragma unroll
+            for (int k = 0; k < kSmallMode; ++k) xv[k] = (k < nin && tid < nfb) ? buf[tid * nin + min(k, nin - 1)] : 0.0;
+            __syncthreads();
+            if (tid < nfb)
+                for (int i = 0; i < nout; ++i) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < kSmallMode; ++k)
+                        if (k < nin) acc = fma(Ms[i * nin + k], xv[k], acc);
+                    buf[tid * nout + i] = alpha * acc;
+                }
+            __syncthreads();
+            const int64_t yb = f0 * nout;
+            for (int e = tid; e < nfb * nout; e += 256) {
+                double val = buf[e];
+                if (beta != 0.0) val += beta * Z[yb + e];
+                Y[yb + e] = val;
+            }
+            __syncthreads();
+        }
+        return;
+    }
     const int64_t nf = L * R;
     for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (int64_t)gridDim.x * blockDim.x) {
         const int64_t l = f / R, r = f - l * R;
