@@ -391,9 +391,12 @@ __device__ inline bool tuple_inverse(double* const (&Ts)[D], const int (&tp)[D],
 // unknown) for launches with few leaves.  The order-3 kernel is held to
 // three waves per SIMD worth of registers; the 256-thread order-4 kernel
 // keeps its 16-unknown tuple solve in registers (one wave per SIMD), the
-// 512-thread one (two waves per SIMD) calls it out of line.
-template <int D, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 : 3))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
+// 512-thread one (two waves per SIMD) calls it out of line.  OCC = 2: the
+// 256-thread order-4 kernel at two waves per SIMD (the 16-unknown solve out
+// of line, some registers spilled), for launches of more than two leaves
+// per CU, where two leaves per CU outrun one faster leaf.
+template <int D, int NT, int OCC = 0>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC ? OCC : (D == 4 ? 1 : 3)))) void leaf_kernel(const LeafDesc* __restrict__ leaves, int64_t first,
                                                       const ProbDesc* __restrict__ probs,
                                                       const LeafShape* __restrict__ shapes,
                                                       const uint16_t* __restrict__ ents,
@@ -844,7 +847,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(D == 4 ? 1 :
                 int e0 = 0;
 #pragma unroll
                 for (int mu = 0; mu < D; ++mu) e0 += a[mu] * ls[mu];
-                if (!coupled_solve<D, (D == 4 && NT > kLeafNT)>(Xs, Ts, tp, ls, a, w, e0)) ok = false;
+                if (!coupled_solve<D, (D == 4 && (NT > kLeafNT || OCC == 2))>(Xs, Ts, tp, ls, a, w, e0)) ok = false;
             }
         }
         __syncthreads();
@@ -902,13 +905,15 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 0;
     const bool wide = !small && cus > 0 && count <= ((D == 4) ? cus / 2 : cus);
+    const bool dense4 = D == 4 && !small && cus > 0 && count > 2 * (int64_t)cus;
     dim3 grid((unsigned)count), block(small ? 64 : (wide ? kLeafNTWide : kLeafNT));
     const void* fn = (D == 3) ? (small ? (const void*)leaf_kernel<3, 64>
                                        : (wide ? (const void*)leaf_kernel<3, kLeafNTWide>
                                                : (const void*)leaf_kernel<3, kLeafNT>))
                               : (small ? (const void*)leaf_kernel<4, 64>
                                        : (wide ? (const void*)leaf_kernel<4, kLeafNTWide>
-                                               : (const void*)leaf_kernel<4, kLeafNT>));
+                                               : (dense4 ? (const void*)leaf_kernel<4, kLeafNT, 2>
+                                                         : (const void*)leaf_kernel<4, kLeafNT>)));
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -928,6 +933,9 @@ hipError_t launch_leaf(int D, const LeafDesc* leaves, int64_t first, int64_t cou
     else if (small)
         hipLaunchKernelGGL((leaf_kernel<4, 64>), grid, block, lds, st, leaves, first, probs, shapes, ents, hoffs,
                            status, geom);
+    else if (dense4)
+        hipLaunchKernelGGL((leaf_kernel<4, kLeafNT, 2>), grid, block, lds, st, leaves, first, probs, shapes, ents,
+                           hoffs, status, geom);
     else
         hipLaunchKernelGGL((leaf_kernel<4, kLeafNT>), grid, block, lds, st, leaves, first, probs, shapes, ents,
                            hoffs, status, geom);
