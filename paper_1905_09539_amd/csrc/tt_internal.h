@@ -121,13 +121,19 @@ __host__ __device__ inline int upd_wide_slots(int P) { return P <= 64 ? 4 : (P <
 
 // Output tiles of an update task: na x nb, item (ta, tb) with ta < na and
 // tb < nb.  At most 16 target rows: 16 x 256 tiles (ta: 256 pencil columns;
-// nb = 1, the item's tb counts the other tasks sharing the tile);
-// more than 64: 128 target rows x 64 pencil columns; else 64 x 64.  For
+// nb = 1, the item's tb counts the other tasks sharing the tile); 17 to 32:
+// 32 x 128 tiles (ta: 128 pencil columns, nb = 1); more than 64: 128
+// target rows x 64 pencil columns; else 64 x 64.  For
 // modes below D - 1, ta counts target rows and tb pencil columns; for the
 // fastest mode (right: MFMA rows are pencil columns) the reverse.
 inline void upd_tile_grid(const UpdDesc& t, bool right, int& na, int& nb) {
     if (t.M <= 16) {
         na = (t.P + 4 * kTile - 1) / (4 * kTile);
+        nb = 1;
+        return;
+    }
+    if (t.M <= 32) {  // 32 target rows x 128 pencil columns: ta counts the columns
+        na = (t.P + 2 * kTile - 1) / (2 * kTile);
         nb = 1;
         return;
     }

@@ -22,7 +22,8 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 // mode 0 (subtract), the accumulator of mode mu otherwise (add, or store for
 // the first contribution).  A 64x64 tile is four 32x32 wave tiles of 2x2
 // MFMA 16x16x4 FP64 blocks (tasks with more than 64 target rows: 128 x 64
-// tiles, two such blocks per wave; at most 16 target rows: 16 x 256 tiles);
+// tiles, two such blocks per wave; 17 to 32 target rows: 32 x 128 tiles; at
+// most 16 target rows: 16 x 256 tiles);
 // K advances in chunks of 16 staged through LDS.
 // For the fastest mode (s_mu = 1) the roles are transposed so that the
 // contiguous index runs along the MFMA columns.
@@ -80,16 +81,17 @@ __device__ inline int mfma_row(int v, int g) {
 
 // One K chunk of a 64x64 tile: each wave's 32x32 block as 2x2 MFMA 16x16x4
 // blocks, operands from LDS.  An operand is staged either as [k][row] with
-// pitch kLdsRow or (ARK / BRK) as [row][k] with pitch kRkRow (odd, so the
-// sixteen rows a lane group reads fall in distinct banks).
+// pitch KP (kLdsRow for 64-wide blocks) or (ARK / BRK) as [row][k] with
+// pitch kRkRow (odd, so the sixteen rows a lane group reads fall in
+// distinct banks).
 constexpr int kRkRow = kKC + 1;
-template <int LP, bool ARK, bool BRK>
+template <int LP, bool ARK, bool BRK, int KP = kLdsRow>
 __device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, int wc, int li, int lk,
                                     typename MfmaAcc<LP>::type (&acc)[2][2]) {
     if constexpr (LP == 2) {
         // one 16x16x16 step: this lane's K values are 4 lk .. 4 lk + 3
-        auto A = [&](int r, int k) { return ARK ? As[r * kRkRow + k] : As[k * kLdsRow + r]; };
-        auto B = [&](int c, int k) { return BRK ? Bs[c * kRkRow + k] : Bs[k * kLdsRow + c]; };
+        auto A = [&](int r, int k) { return ARK ? As[r * kRkRow + k] : As[k * KP + r]; };
+        auto B = [&](int c, int k) { return BRK ? Bs[c * kRkRow + k] : Bs[k * KP + c]; };
         const int k0 = 4 * lk;
         Split4 a[2], b[2];
 #pragma unroll
@@ -106,10 +108,10 @@ __device__ inline void mfma_chunk_l(const double* As, const double* Bs, int wr, 
 #pragma unroll
     for (int kk = 0; kk < kKC; kk += 4) {
         const int k = kk + lk;
-        const double a0 = ARK ? As[(wr + li) * kRkRow + k] : As[k * kLdsRow + wr + li];
-        const double a1 = ARK ? As[(wr + 16 + li) * kRkRow + k] : As[k * kLdsRow + wr + 16 + li];
-        const double b0 = BRK ? Bs[(wc + li) * kRkRow + k] : Bs[k * kLdsRow + wc + li];
-        const double b1 = BRK ? Bs[(wc + 16 + li) * kRkRow + k] : Bs[k * kLdsRow + wc + 16 + li];
+        const double a0 = ARK ? As[(wr + li) * kRkRow + k] : As[k * KP + wr + li];
+        const double a1 = ARK ? As[(wr + 16 + li) * kRkRow + k] : As[k * KP + wr + 16 + li];
+        const double b0 = BRK ? Bs[(wc + li) * kRkRow + k] : Bs[k * KP + wc + li];
+        const double b1 = BRK ? Bs[(wc + 16 + li) * kRkRow + k] : Bs[k * KP + wc + 16 + li];
         if constexpr (LP == 1) {
             const float fa0 = (float)a0, fa1 = (float)a1, fb0 = (float)b0, fb1 = (float)b1;
             acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa0, fb0, acc[0][0], 0, 0, 0);
@@ -494,6 +496,149 @@ __device__ inline void upd_tile(const UpdDesc& t, const WorkItem& wi, const gdou
     }
 }
 
+// Flat tile for updates with 17 to 32 target rows (a 64-row tile would leave
+// half or more of its MFMA rows idle): 32 target rows x 128 pencil columns,
+// each wave a 32x32 block of 2x2 MFMA 16x16 blocks side by side along the
+// pencil columns.  Left path: MFMA rows are the target rows, the pencil
+// block is staged [k][c] at pitch kFlatRow; right path (fastest mode): MFMA
+// rows are pencil columns, both blocks [row][k] at pitch kRkRow.
+constexpr int kFlatCols = 2 * kTile;
+constexpr int kFlatRow = kFlatCols + 16;  // rows k and k+1 in disjoint bank halves
+template <int LP>
+__device__ inline void upd_flat(const UpdDesc& t, const WorkItem& wi, const gdouble* __restrict__ X,
+                                gdouble* __restrict__ C, const gdouble* __restrict__ T, int64_t nmu, int64_t smu,
+                                bool right, bool store, const gdouble* B0, double sgn, double* smem,
+                                int64_t* colOff) {
+    // LDS: left  As = T block [r][k] (32 x kRkRow), Bs = pencil block [k][c] (16 x kFlatRow);
+    //      right As = pencil block [c][k] (128 x kRkRow), Bs = T block [r][k] (32 x kRkRow)
+    constexpr int kBOff = kFlatCols * kRkRow;  // 2176 doubles: the larger first block
+    static_assert(kBOff + kKC * kFlatRow <= kUpdSmemDoubles && kBOff + 32 * kRkRow <= kUpdSmemDoubles,
+                  "flat tile exceeds its LDS buffer");
+    double* As = smem;
+    double* Bs = smem + kBOff;
+    const int tid = threadIdx.x;
+    const int col0 = wi.ta * kFlatCols;  // pencil columns (the only tile index: at most 32 target rows)
+
+    if (tid < kFlatCols) {
+        const int c = col0 + tid;
+        colOff[tid] = (c < t.P) ? pencil_col_offset(t, c) : 0;
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    typename MfmaAcc<LP>::type acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename MfmaAcc<LP>::type{0, 0, 0, 0};
+    const int nchunk = (t.K + kKC - 1) / kKC;
+
+    if (!right) {
+        // loaders: T row tid / 8, K pair tid % 8; pencil column tid % 128,
+        // K rows 8 (tid / 128) .. + 7
+        const int la_r = tid >> 3, la_k = 2 * (tid & 7);
+        const int lb_c = tid & (kFlatCols - 1), lb_k = (tid >> 7) * 8;
+        const bool aval = la_r < t.M;
+        const gdouble* Arow = T + (int64_t)(t.r0 + la_r) * nmu + t.k0 + la_k;
+        const bool bval = (col0 + lb_c) < t.P;
+        const gdouble* Bcol = X + colOff[lb_c] + (int64_t)(t.k0 + lb_k) * smu;
+        double ra0[2], rb0[8], ra1[2], rb1[8];  // two chunks in flight
+        auto gload = [&](double (&ra)[2], double (&rb)[8], int kc) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) ra[e] = *pick(aval && kc + la_k + e < t.K, Arow + kc + e);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) rb[i] = *pick(bval && kc + lb_k + i < t.K, Bcol + (int64_t)(kc + i) * smu);
+        };
+        auto stage = [&](const double (&ra)[2], const double (&rb)[8]) {
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 2; ++e) As[la_r * kRkRow + la_k + e] = ra[e];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[(lb_k + i) * kFlatRow + lb_c] = rb[i];
+            __syncthreads();
+        };
+        const int wc = wave * 32;
+        k_pipeline(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() { mfma_chunk_l<LP, true, false, kFlatRow>(As, Bs, 0, wc, li, lk, acc); });
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = wc + 16 * j + li;
+            if (col0 + c >= t.P) continue;
+            const int64_t coff = colOff[c];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * i + mfma_row<LP>(v, lk);
+                    if (r < t.M) {
+                        const int64_t o = coff + (int64_t)(t.r0 + r) * smu;
+                        const double val = sgn * (double)acc[i][j][v];
+                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
+                    }
+                }
+        }
+    } else {
+        // loaders: rows tid / 8 + 32 j of the pencil block (j < 4) and row
+        // tid / 8 of the T block, K pair tid % 8 (eight lanes per row)
+        const int lr = tid >> 3, rk = 2 * (tid & 7);
+        const gdouble* Xr[4];
+        bool cval[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = lr + 32 * j;
+            cval[j] = (col0 + q) < t.P;
+            Xr[j] = X + colOff[q] + t.k0 + rk;
+        }
+        const bool rval = lr < t.M;
+        const gdouble* Tr = T + (int64_t)(t.r0 + lr) * nmu + t.k0 + rk;
+        double ra0[8], rb0[2], ra1[8], rb1[2];  // two chunks in flight
+        auto gload = [&](double (&ra)[8], double (&rb)[2], int kc) {
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const bool kv = kc + rk + e < t.K;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ra[2 * j + e] = *pick(cval[j] && kv, Xr[j] + kc + e);
+                rb[e] = *pick(rval && kv, Tr + kc + e);
+            }
+        };
+        auto stage = [&](const double (&ra)[8], const double (&rb)[2]) {
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) As[(lr + 32 * j) * kRkRow + rk + e] = ra[2 * j + e];
+                Bs[lr * kRkRow + rk + e] = rb[e];
+            }
+            __syncthreads();
+        };
+        const int wr = wave * 32;
+        k_pipeline(
+            nchunk, [&](int set, int kc) { set ? gload(ra1, rb1, kc) : gload(ra0, rb0, kc); },
+            [&](int set) { set ? stage(ra1, rb1) : stage(ra0, rb0); },
+            [&]() { mfma_chunk_l<LP, true, true>(As, Bs, wr, 0, li, lk, acc); });
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int c = wr + 16 * i + mfma_row<LP>(v, lk);
+                if (col0 + c >= t.P) continue;
+                const int64_t coff = colOff[c];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int r = 16 * j + li;
+                    if (r < t.M) {
+                        const int64_t o = coff + t.r0 + r;
+                        const double val = sgn * (double)acc[i][j][v];
+                        C[o] = store ? (B0 ? B0[o] + val : val) : C[o] + val;
+                    }
+                }
+            }
+    }
+}
+
 template <int LP>
 __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))) void upd_kernel(const UpdDesc* __restrict__ tasks,
                                                           const WorkItem* __restrict__ items,
@@ -525,10 +670,13 @@ __global__ __launch_bounds__(kUpdThreads) __attribute__((amdgpu_waves_per_eu(3))
         upd_wide<LP>(tasks, t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, smem + kWideTDoubles, colOff);
         return;
     }
-    if (t.M > kTile)  // uniform; the planner sizes the task's tiles by the same rule
+    // uniform; the planner sizes the task's tiles by the same rule
+    if (t.M > kTile)
         upd_tile<LP, 2>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, colOff);
-    else
+    else if (t.M > 32)
         upd_tile<LP, 1>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, colOff);
+    else
+        upd_flat<LP>(t, wi, X, C, T, nmu, smu, right, store, B0, sgn, smem, colOff);
 }
 
 __global__ void zero_int_kernel(int* p, int count) {
